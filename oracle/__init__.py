@@ -1,0 +1,335 @@
+"""FP64 CPU oracle of the D3Q27 cumulant LBM with actuator-line coupling.
+
+TEST INFRASTRUCTURE ONLY: plain, slow, obviously-correct reference code
+(written from Sec. 2.1-2.2 of the waLBerla-wind paper, arXiv 2402.13171).
+Only the test-suite, the smoke check and the CPU-baseline leg of the
+benchmark may import this package. It shares no code with the HIP library.
+
+The C sources next to this file are compiled into ``liboracle.so`` by
+:func:`build` (gcc, OpenMP); this module is a ctypes binding to them.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_SRC = ["orc_lattice.c", "orc_mlp.c", "orc_solver.c", "orc_alm.c"]
+
+PERIODIC, INOUT, NOSLIP, FREESLIP = 0, 1, 2, 3
+CLOSURE_NONE, CLOSURE_SMAG, CLOSURE_MLP = 0, 1, 2
+MLP_NPARAM = 1313
+MLP_NBLOB = MLP_NPARAM + 13
+
+
+def build(verbose: bool = False) -> str:
+    """Compile the oracle C sources into liboracle.so (always recompiles)."""
+    cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+           "-ffp-contract=off", "-Wall", "-Wno-unused-function", "-o", _SO]
+    cmd += [os.path.join(_HERE, s) for s in _SRC] + ["-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    return _SO
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build()
+        _lib = C.CDLL(_SO)
+        _declare(_lib)
+    return _lib
+
+
+class Params(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
+                ("omega", C.c_double * 10), ("closure", C.c_int),
+                ("cs", C.c_double), ("bc_x", C.c_int), ("bc_zlo", C.c_int),
+                ("bc_zhi", C.c_int), ("u_in", C.c_double * 3),
+                ("body_force", C.c_double * 3), ("mlp_emulate_bf16", C.c_int)]
+
+
+class RotorDesc(C.Structure):
+    _fields_ = [("hub", C.c_double * 3), ("radius", C.c_double),
+                ("omega_rot", C.c_double), ("azimuth0", C.c_double),
+                ("eps", C.c_double), ("pitch_deg", C.c_double),
+                ("n_blades", C.c_int), ("n_points", C.c_int),
+                ("r", C.POINTER(C.c_double)), ("chord", C.POINTER(C.c_double)),
+                ("twist_deg", C.POINTER(C.c_double)), ("dl", C.POINTER(C.c_double)),
+                ("n_polar", C.c_int), ("alpha_deg", C.POINTER(C.c_double)),
+                ("cl", C.POINTER(C.c_double)), ("cd", C.POINTER(C.c_double))]
+
+
+_D = C.POINTER(C.c_double)
+
+
+def _declare(L):
+    v = None
+    sig = {
+        "orc_lattice": (v, [C.POINTER(C.c_int), _D]),
+        "orc_feq": (v, [C.c_double, _D, _D]),
+        "orc_central_moments_direct": (v, [_D, _D, _D]),
+        "orc_central_moments": (v, [_D, _D, _D]),
+        "orc_central_to_pops": (v, [_D, _D, _D]),
+        "orc_cumulants": (v, [_D, _D]),
+        "orc_cumulants_inverse": (v, [_D, _D]),
+        "orc_relax": (v, [_D, _D, _D]),
+        "orc_collide": (v, [_D, _D, _D, _D]),
+        "orc_smagorinsky_omega": (C.c_double, [_D, C.c_double, C.c_double]),
+        "orc_closure_features": (v, [_D, C.c_double, _D]),
+        "orc_mlp_nu_t": (C.c_double, [_D, _D, C.c_int]),
+        "orc_mlp_omega": (C.c_double, [_D, _D, C.c_double, C.c_int]),
+        "orc_bf16_round": (C.c_double, [C.c_double]),
+        "orc_create": (C.c_void_p, [C.POINTER(Params)]),
+        "orc_destroy": (v, [C.c_void_p]),
+        "orc_cells": (C.c_size_t, [C.c_void_p]),
+        "orc_init_fields": (v, [C.c_void_p, _D, _D]),
+        "orc_set_pops": (v, [C.c_void_p, _D]),
+        "orc_get_pops": (v, [C.c_void_p, _D]),
+        "orc_set_force_field": (v, [C.c_void_p, _D]),
+        "orc_set_inlet_plane": (v, [C.c_void_p, _D]),
+        "orc_set_mlp": (v, [C.c_void_p, _D]),
+        "orc_step": (v, [C.c_void_p, C.c_int]),
+        "orc_get_fields": (v, [C.c_void_p, _D, _D]),
+        "orc_global_moments": (v, [C.c_void_p, _D, _D, _D]),
+        "orc_time": (C.c_long, [C.c_void_p]),
+        "orc_get_force": (v, [C.c_void_p, _D]),
+        "orc_set_rotor": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(RotorDesc)]),
+        "orc_rotor_loads": (v, [C.c_void_p, C.c_int, _D, _D]),
+        "orc_rotor_points": (v, [C.c_void_p, C.c_int, _D]),
+        "orc_trilinear": (v, [C.c_void_p, _D, C.c_int, _D, _D]),
+        "orc_blade_element": (v, [C.c_double, C.c_double, C.c_double, C.c_double,
+                                  C.c_double, C.c_double, C.c_double, C.c_int,
+                                  _D, _D, _D, _D, _D, _D]),
+        "orc_spread_point": (v, [C.c_void_p, _D, _D, C.c_double, _D]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(_D)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+# ---------------------------------------------------------------- single cell
+def lattice():
+    c = np.zeros((27, 3), dtype=np.int32)
+    w = np.zeros(27)
+    lib().orc_lattice(c.ctypes.data_as(C.POINTER(C.c_int)), _p(w))
+    return c, w
+
+
+def feq(rho, u):
+    f = np.zeros(27)
+    lib().orc_feq(float(rho), _p(_f64(u)), _p(f))
+    return f
+
+
+def central_moments(f, u, direct=False):
+    out = np.zeros(27)
+    fn = lib().orc_central_moments_direct if direct else lib().orc_central_moments
+    fn(_p(_f64(f)), _p(_f64(u)), _p(out))
+    return out
+
+
+def central_to_pops(kappa, u):
+    out = np.zeros(27)
+    lib().orc_central_to_pops(_p(_f64(kappa)), _p(_f64(u)), _p(out))
+    return out
+
+
+def cumulants(kappa):
+    out = np.zeros(27)
+    lib().orc_cumulants(_p(_f64(kappa)), _p(out))
+    return out
+
+
+def cumulants_inverse(C_):
+    out = np.zeros(27)
+    lib().orc_cumulants_inverse(_p(_f64(C_)), _p(out))
+    return out
+
+
+def relax(C_, omega):
+    out = np.zeros(27)
+    lib().orc_relax(_p(_f64(C_)), _p(_f64(omega)), _p(out))
+    return out
+
+
+def collide(f, F, omega):
+    out = np.zeros(27)
+    om = np.ones(10)
+    om[: len(omega)] = omega
+    lib().orc_collide(_p(_f64(f)), _p(_f64(F)), _p(om), _p(out))
+    return out
+
+
+def smagorinsky_omega(kappa, omega0, cs):
+    return lib().orc_smagorinsky_omega(_p(_f64(kappa)), float(omega0), float(cs))
+
+
+def closure_features(kappa, omega0):
+    out = np.zeros(6)
+    lib().orc_closure_features(_p(_f64(kappa)), float(omega0), _p(out))
+    return out
+
+
+def mlp_nu_t(blob, feat, emulate_bf16=False):
+    return lib().orc_mlp_nu_t(_p(_f64(blob)), _p(_f64(feat)), int(emulate_bf16))
+
+
+def bf16_round(x):
+    return lib().orc_bf16_round(float(x))
+
+
+def blade_element(rho, wn, wt, chord, dl, twist_deg, pitch_deg, polar):
+    a, cl, cd = (_f64(polar[k]) for k in ("alpha_deg", "cl", "cd"))
+    fn, ft, al = C.c_double(), C.c_double(), C.c_double()
+    lib().orc_blade_element(float(rho), float(wn), float(wt), float(chord),
+                            float(dl), float(twist_deg), float(pitch_deg), len(a),
+                            _p(a), _p(cl), _p(cd), C.byref(fn), C.byref(ft),
+                            C.byref(al))
+    return fn.value, ft.value, al.value
+
+
+# ---------------------------------------------------------------- domain solver
+class Grid:
+    """Two-array FP64 solver on an nx x ny x nz box (x fastest)."""
+
+    def __init__(self, nx, ny, nz, omega=1.9, omega_hi=None, closure=CLOSURE_NONE,
+                 cs=0.1, bc_x=PERIODIC, bc_zlo=PERIODIC, bc_zhi=PERIODIC,
+                 u_in=(0.0, 0.0, 0.0), body_force=(0.0, 0.0, 0.0),
+                 mlp_emulate_bf16=False):
+        p = Params()
+        p.nx, p.ny, p.nz = nx, ny, nz
+        om = [omega] + list(omega_hi if omega_hi is not None else [1.0] * 9)
+        for k in range(10):
+            p.omega[k] = om[k]
+        p.closure, p.cs = closure, cs
+        p.bc_x, p.bc_zlo, p.bc_zhi = bc_x, bc_zlo, bc_zhi
+        for k in range(3):
+            p.u_in[k] = u_in[k]
+            p.body_force[k] = body_force[k]
+        p.mlp_emulate_bf16 = int(mlp_emulate_bf16)
+        self.shape = (nz, ny, nx)
+        self.n = nx * ny * nz
+        self._h = lib().orc_create(C.byref(p))
+        if not self._h:
+            raise ValueError("oracle: invalid grid parameters")
+        self._keep = []
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().orc_destroy(h)
+            self._h = None
+
+    def init_fields(self, rho, u):
+        rho = _f64(np.broadcast_to(rho, self.shape)).reshape(-1)
+        u = _f64(u).reshape(3, -1)
+        lib().orc_init_fields(self._h, _p(rho), _p(u))
+
+    def set_pops(self, f):
+        lib().orc_set_pops(self._h, _p(_f64(f).reshape(-1)))
+
+    def get_pops(self):
+        f = np.zeros((27,) + self.shape)
+        lib().orc_get_pops(self._h, _p(f))
+        return f
+
+    def set_force_field(self, F):
+        lib().orc_set_force_field(self._h, _p(_f64(F).reshape(-1)))
+
+    def set_inlet_plane(self, u):
+        lib().orc_set_inlet_plane(self._h, _p(_f64(u).reshape(-1)))
+
+    def set_mlp(self, blob):
+        b = _f64(blob)
+        assert b.size == MLP_NBLOB
+        lib().orc_set_mlp(self._h, _p(b))
+
+    def step(self, n=1):
+        lib().orc_step(self._h, int(n))
+
+    @property
+    def time(self):
+        return lib().orc_time(self._h)
+
+    def fields(self):
+        rho = np.zeros(self.shape)
+        u = np.zeros((3,) + self.shape)
+        lib().orc_get_fields(self._h, _p(rho), _p(u))
+        return rho, u
+
+    def force(self):
+        F = np.zeros((3,) + self.shape)
+        lib().orc_get_force(self._h, _p(F))
+        return F
+
+    def global_moments(self):
+        m, mom, e = C.c_double(), np.zeros(3), C.c_double()
+        lib().orc_global_moments(self._h, C.byref(m), _p(mom), C.byref(e))
+        return m.value, mom, e.value
+
+    def set_rotor(self, rid, rotor):
+        """rotor: dict as produced by workloads.rotor (hub, radius, ...)."""
+        arrs = {k: _f64(rotor[k]) for k in ("r", "chord", "twist_deg", "dl")}
+        pol = {k: _f64(rotor["polar"][k]) for k in ("alpha_deg", "cl", "cd")}
+        self._keep += list(arrs.values()) + list(pol.values())
+        d = RotorDesc()
+        for k in range(3):
+            d.hub[k] = rotor["hub"][k]
+        d.radius = rotor["radius"]
+        d.omega_rot = rotor["omega_rot"]
+        d.azimuth0 = rotor.get("azimuth0", 0.0)
+        d.eps = rotor["eps"]
+        d.pitch_deg = rotor.get("pitch_deg", 0.0)
+        d.n_blades = rotor["n_blades"]
+        d.n_points = len(arrs["r"])
+        d.r, d.chord = _p(arrs["r"]), _p(arrs["chord"])
+        d.twist_deg, d.dl = _p(arrs["twist_deg"]), _p(arrs["dl"])
+        d.n_polar = len(pol["alpha_deg"])
+        d.alpha_deg, d.cl, d.cd = _p(pol["alpha_deg"]), _p(pol["cl"]), _p(pol["cd"])
+        if lib().orc_set_rotor(self._h, rid, C.byref(d)) != 0:
+            raise ValueError("oracle: bad rotor")
+        self._rotor_np = getattr(self, "_rotor_np", {})
+        self._rotor_np[rid] = rotor["n_blades"] * len(arrs["r"])
+
+    def rotor_loads(self, rid, with_points=False):
+        out = np.zeros(3)
+        npts = self._rotor_np[rid]
+        pf = np.zeros((npts, 3))
+        lib().orc_rotor_loads(self._h, rid, _p(out), _p(pf))
+        return (out, pf) if with_points else out
+
+    def rotor_points(self, rid):
+        pos = np.zeros((self._rotor_np[rid], 3))
+        lib().orc_rotor_points(self._h, rid, _p(pos))
+        return pos
+
+    def trilinear(self, field, x):
+        field = _f64(field)
+        ncomp = field.size // self.n
+        out = np.zeros(ncomp)
+        lib().orc_trilinear(self._h, _p(field.reshape(-1)), ncomp, _p(_f64(x)), _p(out))
+        return out
+
+    def spread_point(self, xp, Fp, eps):
+        F = np.zeros((3,) + self.shape)
+        lib().orc_spread_point(self._h, _p(_f64(xp)), _p(_f64(Fp)), float(eps), _p(F))
+        return F

@@ -1,0 +1,119 @@
+/*
+ * FP64 CPU oracle for the D3Q27 cumulant lattice-Boltzmann method with
+ * actuator-line coupling (Sec. 2.1 and Sec. 2.2 of the waLBerla-wind paper,
+ * arXiv 2402.13171).
+ *
+ * TEST INFRASTRUCTURE ONLY. This code is plain, slow and written to be read
+ * against the paper; it shares no source with the HIP library and is only
+ * ever loaded by the test-suite, the smoke check and the CPU-baseline leg of
+ * the benchmark.
+ *
+ * Conventions
+ *   velocity index   i = (cx+1) + 3(cy+1) + 9(cz+1), c in {-1,0,1}^3
+ *   opposite         ibar = 26 - i
+ *   moment index     m = a + 3b + 9c for the moment of order (a,b,c),
+ *                    a,b,c in {0,1,2}
+ *   population array f[i*n + cell], cell = x + nx*(y + ny*z) (x fastest)
+ *   lattice units    dx = dt = 1, c_s^2 = 1/3
+ */
+#ifndef ORC_H
+#define ORC_H
+#include <stddef.h>
+
+#define ORC_Q 27
+
+/* boundary kinds (x: periodic or inflow/outflow; z sides: periodic,
+ * halfway bounce-back, free-slip; y is always periodic) */
+enum { ORC_PERIODIC = 0, ORC_INOUT = 1, ORC_NOSLIP = 2, ORC_FREESLIP = 3 };
+enum { ORC_CLOSURE_NONE = 0, ORC_CLOSURE_SMAG = 1, ORC_CLOSURE_MLP = 2 };
+
+/* ---- single-cell building blocks (orc_lattice.c) ---- */
+void   orc_lattice(int c[ORC_Q][3], double w[ORC_Q]);
+void   orc_feq(double rho, const double u[3], double f[ORC_Q]);
+void   orc_central_moments_direct(const double f[ORC_Q], const double u[3],
+                                  double kappa[ORC_Q]);
+void   orc_central_moments(const double f[ORC_Q], const double u[3],
+                           double kappa[ORC_Q]);
+void   orc_central_to_pops(const double kappa[ORC_Q], const double u[3],
+                           double f[ORC_Q]);
+void   orc_cumulants(const double kappa[ORC_Q], double C[ORC_Q]);
+void   orc_cumulants_inverse(const double C[ORC_Q], double kappa[ORC_Q]);
+void   orc_relax(const double C[ORC_Q], const double omega[10],
+                 double Cs[ORC_Q]);
+void   orc_collide(const double f[ORC_Q], const double F[3],
+                   const double omega[10], double fout[ORC_Q]);
+double orc_smagorinsky_omega(const double kappa[ORC_Q], double omega0,
+                             double cs);
+void   orc_closure_features(const double kappa[ORC_Q], double omega0,
+                            double feat[6]);
+
+/* ---- learned closure network (orc_mlp.c) ---- */
+#define ORC_MLP_NPARAM 1313
+#define ORC_MLP_NBLOB  (ORC_MLP_NPARAM + 13)
+double orc_mlp_nu_t(const double *blob, const double feat[6], int emulate_bf16);
+double orc_mlp_omega(const double *blob, const double kappa[ORC_Q],
+                     double omega0, int emulate_bf16);
+double orc_bf16_round(double x);
+
+/* ---- whole-domain solver (orc_solver.c) ---- */
+typedef struct {
+    int nx, ny, nz;
+    double omega[10];      /* omega[0] = shear rate; omega[1..9] higher */
+    int closure;           /* ORC_CLOSURE_* */
+    double cs;             /* Smagorinsky constant */
+    int bc_x;              /* ORC_PERIODIC or ORC_INOUT */
+    int bc_zlo, bc_zhi;    /* ORC_PERIODIC, ORC_NOSLIP or ORC_FREESLIP */
+    double u_in[3];        /* uniform inlet velocity */
+    double body_force[3];  /* uniform body force */
+    int mlp_emulate_bf16;  /* closure network arithmetic: 0 FP64, 1 BF16 emulation */
+} orc_params;
+
+typedef struct orc_grid orc_grid;
+
+orc_grid *orc_create(const orc_params *p);
+void   orc_destroy(orc_grid *g);
+size_t orc_cells(const orc_grid *g);
+void   orc_init_fields(orc_grid *g, const double *rho, const double *u);
+void   orc_set_pops(orc_grid *g, const double *f);
+void   orc_get_pops(const orc_grid *g, double *f);
+void   orc_set_force_field(orc_grid *g, const double *F);
+void   orc_set_inlet_plane(orc_grid *g, const double *u);
+void   orc_set_mlp(orc_grid *g, const double *blob);
+void   orc_step(orc_grid *g, int nsteps);
+void   orc_get_fields(const orc_grid *g, double *rho, double *u);
+void   orc_global_moments(const orc_grid *g, double *mass, double mom[3],
+                          double *ke);
+long   orc_time(const orc_grid *g);
+void   orc_get_force(const orc_grid *g, double *F);
+
+/* ---- actuator line (orc_alm.c) ---- */
+#define ORC_MAX_ROTORS 8
+typedef struct {
+    double hub[3];
+    double radius, omega_rot, azimuth0, eps, pitch_deg;
+    int n_blades, n_points;
+    const double *r, *chord, *twist_deg, *dl;  /* n_points each */
+    int n_polar;
+    const double *alpha_deg, *cl, *cd;          /* uniform alpha grid */
+} orc_rotor_desc;
+
+int  orc_set_rotor(orc_grid *g, int id, const orc_rotor_desc *d);
+void orc_rotor_loads(const orc_grid *g, int id, double out[3], double *pt_force);
+void orc_rotor_points(const orc_grid *g, int id, double *pos);
+
+/* single-point helpers exposed for the unit pins */
+void orc_trilinear(const orc_grid *g, const double *field, int ncomp,
+                   const double x[3], double *out);
+void orc_blade_element(double rho, const double urel_axial,
+                       const double urel_tan, double chord, double dl,
+                       double twist_deg, double pitch_deg, int n_polar,
+                       const double *alpha_deg, const double *cl,
+                       const double *cd, double *Fn, double *Ft,
+                       double *alpha_out);
+void orc_spread_point(const orc_grid *g, const double xp[3],
+                      const double Fp[3], double eps, double *F);
+
+/* internal: the ALM sub-steps of one time step, called by orc_step */
+void orc_alm_step(orc_grid *g);
+
+#endif
