@@ -1,0 +1,150 @@
+"""Benchmark: MLUPS and HBM-roofline fraction of the fused D3Q27 cumulant
+stream-collide on a 512^3 periodic box (seeded random-phase velocity field,
+spectrum k^4 exp(-2 (k/8)^2), u_rms 0.03, omega 1.9), populations stored in
+FP32 (the reported value) and as FP16 / BF16 deviations (variants).
+
+One step = one lbm_step(1): the whole per-step kernel sequence of the path
+for this workload (one fused stream-collide launch; no rotor, no closure in
+the base case). Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_2402_13171_amd import roofline  # noqa: E402
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def time_variant(n, rho, u, storage, closure, steps, warmup, blob=None):
+    import torch
+    from paper_2402_13171_amd.lbm import Lbm
+    sim = Lbm(n, n, n, omega=1.9, storage=storage, closure=closure, cs_smag=0.1)
+    if blob is not None:
+        sim.set_closure_weights(blob)
+    sim.init_fields(rho, u)
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(sim.stream)
+    t0 = time.perf_counter()
+    sim.step(steps)
+    e1.record(sim.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    m, mom, ke = sim.global_moments()
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    mlups = n ** 3 * steps / (ms * 1e-3) / 1e6
+    return {"mlups": mlups, "ms_per_step": ms / steps, "wall_s": wall, "mass": m, "ke": ke}
+
+
+def cpu_baseline(sample_n=128, steps=100):
+    """The FP64 oracle on the host cores, on a bounded sample of the same
+    recipe (a sample_n^3 periodic box, same spectrum and omega)."""
+    import oracle
+    import workloads
+    rho, u = workloads.random_phase_field(sample_n, seed=0)
+    g = oracle.Grid(sample_n, sample_n, sample_n, omega=1.9)
+    g.init_fields(rho, u)
+    g.step(1)  # warm-up
+    t0 = time.perf_counter()
+    g.step(steps)
+    dt = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": sample_n ** 3 * steps / dt / 1e6, "unit": "MLUPS", "cores": cores,
+            "kind": "oracle",
+            "sample": f"{sample_n}^3 periodic box of the same random-phase recipe, {steps} steps, "
+                      f"FP64 two-array oracle ({dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--variants", default="f32,f16,bf16,f32+smag")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import workloads
+    n = args.n
+    log(f"bench: generating {n}^3 random-phase field (seed 0)")
+    t0 = time.perf_counter()
+    rho, u = workloads.random_phase_field(n, seed=0)
+    log(f"bench: field ready in {time.perf_counter() - t0:.1f} s")
+
+    results = {}
+    for v in args.variants.split(","):
+        storage, _, closure = v.partition("+")
+        closure = closure or "none"
+        log(f"bench: variant {v}: {args.warmup} warm-up + {args.steps} timed steps")
+        r = time_variant(n, rho, u, storage, closure, args.steps, args.warmup)
+        s_bytes = 4 if storage == "f32" else 2
+        nb = roofline.bytes_per_lup(s_bytes)
+        bw = roofline.achieved_bandwidth(r["mlups"] * 1e6, nb)
+        r.update({"bytes_per_lup": nb, "achieved_GBps": bw / 1e9,
+                  "hbm_frac": bw / roofline.HBM_PEAK_BPS})
+        results[v] = r
+        log(f"bench: {v}: {r['mlups']:.0f} MLUPS, {r['ms_per_step']:.3f} ms/step, "
+            f"{bw / 1e9:.0f} GB/s algorithmic ({100 * bw / roofline.HBM_PEAK_BPS:.1f}% of 8 TB/s)")
+
+    base = results.get("f32") or next(iter(results.values()))
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("bench: timing the CPU oracle on a bounded sample")
+        cpu = cpu_baseline()
+        log(f"bench: oracle {cpu['value']:.2f} MLUPS on {cpu['cores']} cores")
+
+    nb = base["bytes_per_lup"]
+    out = {
+        "metric": "MLUPS & % HBM roofline, D3Q27 512^3: FP32 vs FP16-store(+learned closure)",
+        "value": round(base["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(base["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"D3Q27 cumulant, {n}^3 periodic, random-phase field seed 0 "
+                               "(k^4 exp(-2(k/8)^2), u_rms 0.03), omega 1.9, FP32-stored populations",
+                   "n": n, "storage": "f32", "closure": "none", "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(base["achieved_GBps"], 1),
+                     "peak": roofline.HBM_PEAK_BPS / 1e9, "unit": "GB/s",
+                     "frac": round(base["hbm_frac"], 4), "traffic": None,
+                     "kernel": "k_stream_collide", "bytes_per_lup": nb,
+                     "bytes_per_launch": nb * n ** 3},
+        "cpu_baseline": cpu,
+        "variants": {k: {"mlups": round(v["mlups"], 1), "ms_per_step": round(v["ms_per_step"], 4),
+                         "achieved_GBps": round(v["achieved_GBps"], 1),
+                         "hbm_frac": round(v["hbm_frac"], 4), "bytes_per_lup": v["bytes_per_lup"],
+                         "ratio_vs_f32": round(v["mlups"] / base["mlups"], 3)}
+                     for k, v in results.items()},
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,168 @@
+/*
+ * lbm.h - C ABI of the MI355X D3Q27 cumulant lattice-Boltzmann solver with
+ * actuator-line rotor coupling (after the waLBerla-wind method of
+ * arXiv 2402.13171).
+ *
+ * What the library computes
+ *   One time step is eq. (1) of Sec. 2.1: the cumulant collision (Sec. 2.1,
+ *   Geier et al. 2015) with a Guo-type force, followed by streaming on the
+ *   D3Q27 lattice. When rotors are set, each step first runs the actuator
+ *   line of Sec. 2.2: rotor kinematics (Alg. 2 in closed form), trilinear
+ *   sampling of density and velocity at the blade points, blade-element
+ *   forces from tabulated lift/drag polars (the force equation of
+ *   Sec. 2.2), and projection of the reaction force onto the lattice with a
+ *   normalised Gaussian kernel. Optional eddy-viscosity closures set the
+ *   shear rate per cell (Smagorinsky, or a learned per-cell network).
+ *
+ * Conventions
+ *   - Lattice units: dx = dt = 1, c_s^2 = 1/3. Cell (x,y,z) sits at integer
+ *     coordinates; x is the fastest index; cell = x + nx*(y + ny*z).
+ *   - Velocity index i = (cx+1) + 3(cy+1) + 9(cz+1); opposite is 26 - i.
+ *   - Host field arrays are FP64: rho[n], u[3][n] (ux block, uy block, uz
+ *     block), F[3][n]; populations f[27][n].
+ *   - Every function returns an lbm_status (0 = LBM_OK, < 0 = error). No
+ *     function throws or aborts; after an error, lbm_last_error(ctx) gives a
+ *     message. Arguments are validated before any device work.
+ *   - Device memory for the populations and the small auxiliary area is
+ *     owned by the caller (e.g. PyTorch) and handed over with lbm_attach; it
+ *     must stay valid until lbm_destroy. Rotor, closure and staging buffers
+ *     are owned by the context. Host arrays passed in are copied before the
+ *     call returns; host output buffers are owned by the caller.
+ *   - Work is enqueued on the stream given in lbm_config (NULL: the library
+ *     creates one). Calls that return host data synchronise that stream.
+ *   - A context is not thread safe; distinct contexts are independent.
+ */
+#ifndef LBM_H
+#define LBM_H
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx lbm_ctx;
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_EINVAL = -1,      /* invalid argument or configuration */
+    LBM_ENOMEM = -2,      /* a device or host allocation failed */
+    LBM_EHIP = -3,        /* a HIP runtime call failed */
+    LBM_EUNSTABLE = -4,   /* the mass / NaN check of lbm_step fired */
+    LBM_ESTATE = -5       /* call out of order (e.g. before lbm_attach) */
+} lbm_status;
+
+typedef enum { LBM_F32 = 0, LBM_F16 = 1, LBM_BF16 = 2 } lbm_storage;
+typedef enum { LBM_CLOSURE_NONE = 0, LBM_CLOSURE_SMAG = 1, LBM_CLOSURE_MLP = 2 } lbm_closure;
+typedef enum {
+    LBM_BC_PERIODIC = 0,
+    LBM_BC_INFLOW_OUTFLOW = 1, /* x only: equilibrium inlet at x=-1 (density 1,
+                                  inlet velocity), zero-gradient outlet at x=nx */
+    LBM_BC_NOSLIP = 2,         /* z sides: halfway bounce-back */
+    LBM_BC_FREESLIP = 3        /* z sides: specular reflection */
+} lbm_bc;
+
+typedef struct {
+    int nx, ny, nz;        /* cells; each >= 2, nx*ny*nz < 2^32 */
+    double omega;          /* shear relaxation rate omega_1, 0 < omega < 2 */
+    double omega_hi[9];    /* omega_2..omega_10 (bulk, 3rd..6th order); an
+                              entry of 0 means the default 1.0 */
+    int storage;           /* lbm_storage: populations are stored as the
+                              deviation f_i - w_i in this type */
+    int closure;           /* lbm_closure */
+    double cs_smag;        /* Smagorinsky constant for LBM_CLOSURE_SMAG */
+    int bc_x;              /* LBM_BC_PERIODIC or LBM_BC_INFLOW_OUTFLOW */
+    int bc_z_lo, bc_z_hi;  /* LBM_BC_PERIODIC (both), NOSLIP or FREESLIP */
+    double u_in[3];        /* uniform inlet velocity (bc_x inflow/outflow) */
+    double body_force[3];  /* uniform body force per cell */
+    int check_every;       /* FP64 mass/NaN check period in steps; 0 = off */
+    void *stream;          /* hipStream_t, or NULL */
+} lbm_config;
+
+/* Create a context (validates cfg; no device memory is touched yet). */
+int lbm_create(const lbm_config *cfg, lbm_ctx **out);
+int lbm_destroy(lbm_ctx *ctx);
+
+/* Bytes of caller-owned device memory lbm_attach needs: the population
+ * store (27 planes of n values of the storage type, plane stride rounded up
+ * to 256 bytes) and the auxiliary area (outflow ghost plane, inlet plane,
+ * reduction partials and flags). */
+int lbm_required_bytes(const lbm_ctx *ctx, size_t *pop_bytes, size_t *aux_bytes);
+
+/* Hand over device buffers of at least the required sizes, 256-byte aligned. */
+int lbm_attach(lbm_ctx *ctx, void *d_pops, void *d_aux);
+
+/* Taylor-Green vortex u = u0 sin kx cos ky cos kz, v = -u0 cos kx sin ky cos kz,
+ * w = 0, density rho0, populations at equilibrium; resets time to 0. */
+int lbm_init_tgv(lbm_ctx *ctx, double u0, double k, double rho0);
+
+/* Equilibrium populations from host FP64 density rho[n] and velocity u[3][n];
+ * resets time to 0. */
+int lbm_init_fields(lbm_ctx *ctx, const double *rho, const double *u);
+
+/* Actuator-line rotor: rigid blades turning about the +x axis through hub.
+ * r, chord, twist_deg, dl: n_points values per blade (element centre radius,
+ * chord, twist in degrees, element length). Polars: n_polar >= 2 values of
+ * C_L and C_D on a uniform grid alpha_deg[] (ascending), interpolated
+ * linearly, end values outside. Blade b sits at azimuth
+ * azimuth0 + omega_rot * t + 2 pi b / n_blades, measured from +y towards +z.
+ * eps is the Gaussian kernel width (support: 13 nodes per axis around the
+ * nearest node). All arrays are copied. rotor_id in [0, 8). The rotor's
+ * spreading box must lie inside the domain. */
+typedef struct {
+    double hub[3];
+    double axis[3];        /* must be (1, 0, 0) */
+    double radius, omega_rot, azimuth0, eps, pitch_deg;
+    int n_blades, n_points;
+    const double *r, *chord, *twist_deg, *dl;
+    int n_polar;
+    const double *alpha_deg, *cl, *cd;
+} lbm_rotor;
+int lbm_set_rotor(lbm_ctx *ctx, int rotor_id, const lbm_rotor *rotor);
+
+/* Enqueue n time steps. With check_every > 0, an FP64 mass and NaN check
+ * runs every check_every steps and at the end; the call then synchronises
+ * and returns LBM_EUNSTABLE if a check failed. */
+int lbm_step(lbm_ctx *ctx, int n);
+
+/* Density and velocity at the current time, u = (sum c f + F/2)/rho with
+ * the force of the last step, into host rho[n] and u[3][n]. Synchronises. */
+int lbm_get_fields(lbm_ctx *ctx, double *rho, double *u);
+
+/* Thrust (axial force on the blades), torque about the axis and power
+ * (torque * omega_rot) of the last step; pt_force (nullable) receives the
+ * force on each blade point, [n_blades*n_points][3]. Synchronises. */
+int lbm_rotor_loads(lbm_ctx *ctx, int rotor_id, double out[3], double *pt_force);
+
+/* FP64 totals over the domain: mass sum rho, momentum sum rho u, kinetic
+ * energy 1/2 sum rho |u|^2. Synchronises. */
+int lbm_global_moments(lbm_ctx *ctx, double *mass, double mom[3], double *kin_energy);
+
+/* Populations f_i (not shifted) at the current time in natural layout, host
+ * FP64 f[27][n]. Synchronises. */
+int lbm_get_pops(lbm_ctx *ctx, double *f);
+
+/* Number of completed steps. */
+int lbm_time(const lbm_ctx *ctx, long *t);
+
+/* Dense body-force field, host FP64 F[3][n], added to body_force in every
+ * cell (e.g. Kolmogorov forcing); NULL removes it. */
+int lbm_set_force_field(lbm_ctx *ctx, const double *F);
+
+/* Closure network parameters (1326 floats: W1[32][6] b1[32] W2[32][32]
+ * b2[32] w3[32] b3 mu[6] sigma[6] nu_scale); the matrix weights are used in
+ * bfloat16 on the matrix cores, the rest in float32. */
+int lbm_set_closure_weights(lbm_ctx *ctx, const float *w, size_t n);
+
+/* Checkpoint: raw population store, outflow ghost plane, time and layout
+ * parity. lbm_state_bytes gives the size. Synchronises. */
+int lbm_state_bytes(const lbm_ctx *ctx, size_t *bytes);
+int lbm_get_state(lbm_ctx *ctx, void *host_buf, size_t bytes);
+int lbm_set_state(lbm_ctx *ctx, const void *host_buf, size_t bytes);
+
+const char *lbm_strerror(int code);
+const char *lbm_last_error(const lbm_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -131,7 +131,7 @@ static double polar(double a, int n, const double *alpha, const double *v)
 {
     double da = (alpha[n - 1] - alpha[0]) / (n - 1);
     double s = (a - alpha[0]) / da;
-    if (s <= 0.0)
+    if (!(s > 0.0)) /* also NaN */
         return v[0];
     if (s >= n - 1)
         return v[n - 1];

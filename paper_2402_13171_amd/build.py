@@ -1,0 +1,50 @@
+"""Build the HIP shared library liblbm.so for gfx950 (in-tree)."""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+SO = os.path.join(HERE, "liblbm.so")
+SOURCES = ["lbm_lattice.hip", "lbm_alm.hip", "lbm_mlp.hip", "lbm_api.hip"]
+
+HIPCC_FLAGS = [
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    # keep the compiler from emitting packed FP32 arithmetic
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
+]
+
+
+def build(verbose: bool = False, jobs: int = 4) -> str:
+    """Compile every HIP source to an object in parallel, then link."""
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
+    procs, objs = [], []
+    for s in srcs:
+        obj = os.path.join(objdir, s.replace(".hip", ".o"))
+        objs.append(obj)
+        cmd = [hipcc] + [f for f in HIPCC_FLAGS if f != "-shared"] + ["-c", os.path.join(CSRC, s), "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((s, subprocess.Popen(cmd)))
+        if len([p for _, p in procs if p.poll() is None]) >= jobs:
+            for _, p in procs:
+                p.wait()
+    bad = [s for s, p in procs if p.wait() != 0]
+    if bad:
+        raise RuntimeError(f"hipcc failed for {bad}")
+    link = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", SO + ".tmp"] + objs
+    if verbose:
+        print(" ".join(link), flush=True)
+    subprocess.run(link, check=True)
+    os.replace(SO + ".tmp", SO)
+    return SO
+
+
+if __name__ == "__main__":
+    build(verbose="-v" in sys.argv)

@@ -1,0 +1,191 @@
+// Actuator-line kernels (Sec. 2.2 of the waLBerla-wind paper): per step, one
+// workgroup per rotor computes blade-point kinematics, stages the density and
+// velocity of the 8 cells around every point in LDS, interpolates them
+// trilinearly, evaluates the blade-element force and reduces thrust and
+// torque in FP64; a second kernel spreads the reaction force onto the
+// rotor's box of cells in gather form (no atomics, deterministic).
+#include "lbm_access.h"
+
+namespace lbm {
+
+constexpr int ALM_BLOCK = 256;
+constexpr int ALM_MAX_PTS = 512;
+constexpr double PI_D = 3.14159265358979323846;
+
+__device__ __forceinline__ double polar_lookup(double a, const RotorDev &R, const float *tab) {
+    const double s = (a - R.alpha0) / R.dalpha;
+    if (!(s > 0.0)) return tab[0];  // also catches NaN: the index below stays in range
+    if (s >= R.n_polar - 1) return tab[R.n_polar - 1];
+    int k = (int)floor(s);
+    if (k > R.n_polar - 2) k = R.n_polar - 2;
+    const double t = s - k;
+    return (double)tab[k] * (1.0 - t) + (double)tab[k + 1] * t;
+}
+
+__device__ __forceinline__ int wrap_any(int v, int n) { return ((v % n) + n) % n; }
+
+// one workgroup per rotor
+template <typename T, int PAR>
+__global__ __launch_bounds__(ALM_BLOCK) void k_alm_points(Geo g, Physics ph, RotorDev *rots, long t) {
+    RotorDev &R = rots[blockIdx.x];
+    const int npts = R.n_blades * R.n_points;
+    __shared__ double s_corner[ALM_BLOCK][4];  // rho, u of one corner cell per work item
+    __shared__ double s_red[ALM_BLOCK][2];
+    double accT = 0.0, accQ = 0.0;
+
+    // points are processed in batches of ALM_BLOCK/8 (eight corner cells per point)
+    const int per_batch = ALM_BLOCK / 8;
+    for (int base = 0; base < npts; base += per_batch) {
+        // stage: thread -> (point, corner)
+        {
+            const int p = base + threadIdx.x / 8, corner = threadIdx.x % 8;
+            if (p < npts) {
+                const int b = p / R.n_points, k = p % R.n_points;
+                const double th = R.azimuth0 + R.omega_rot * (double)t + 2.0 * PI_D * b / R.n_blades;
+                const double rr = R.r[k];
+                const double xp[3] = {R.hub[0], R.hub[1] + rr * cos(th), R.hub[2] + rr * sin(th)};
+                const int dx = corner & 1, dy = (corner >> 1) & 1, dz = corner >> 2;
+                const int cx = wrap_any((int)floor(xp[0]) + dx, g.nx);
+                const int cy = wrap_any((int)floor(xp[1]) + dy, g.ny);
+                const int cz = wrap_any((int)floor(xp[2]) + dz, g.nz);
+                double r, ux, uy, uz;
+                cell_macro<T, PAR>(g, ph, ((size_t)cz * g.ny + cy) * g.nx + cx, cx, cy, cz, r, ux, uy, uz);
+                s_corner[threadIdx.x][0] = r;
+                s_corner[threadIdx.x][1] = ux;
+                s_corner[threadIdx.x][2] = uy;
+                s_corner[threadIdx.x][3] = uz;
+            }
+        }
+        __syncthreads();
+        // interpolate + blade element: one thread per point
+        if (threadIdx.x < per_batch && base + threadIdx.x < npts) {
+            const int p = base + threadIdx.x;
+            const int b = p / R.n_points, k = p % R.n_points;
+            const double th = R.azimuth0 + R.omega_rot * (double)t + 2.0 * PI_D * b / R.n_blades;
+            const double ct = cos(th), st = sin(th);
+            const double rr = R.r[k];
+            const double xp[3] = {R.hub[0], R.hub[1] + rr * ct, R.hub[2] + rr * st};
+            double fr[3];
+            for (int a = 0; a < 3; ++a) fr[a] = xp[a] - floor(xp[a]);
+            double s[4] = {0, 0, 0, 0};
+            for (int c = 0; c < 8; ++c) {
+                const int dx = c & 1, dy = (c >> 1) & 1, dz = c >> 2;
+                const double w = (dx ? fr[0] : 1.0 - fr[0]) * (dy ? fr[1] : 1.0 - fr[1]) * (dz ? fr[2] : 1.0 - fr[2]);
+                for (int q = 0; q < 4; ++q) s[q] += w * s_corner[threadIdx.x * 8 + c][q];
+            }
+            const double rho = s[0];
+            // e_theta = (0, -sin, cos); relative in-plane wind W = W_n e_x - W_t e_theta
+            const double ut = -s[2] * st + s[3] * ct;
+            const double wn = s[1];
+            const double wt = -(ut - R.omega_rot * rr);
+            double a = atan2(wn, wt) * (180.0 / PI_D) - R.twist[k] - R.pitch_deg;
+            // |phi| <= 180 and |twist + pitch| < 180: one correction wraps to [-180, 180)
+            if (a >= 180.0) a -= 360.0;
+            else if (a < -180.0) a += 360.0;
+            const double CL = polar_lookup(a, R, R.cl), CD = polar_lookup(a, R, R.cd);
+            const double w2 = wn * wn + wt * wt, wm = sqrt(w2);
+            const double q = 0.5 * rho * w2 * R.chord[k] * R.dl[k];
+            double Fn = 0.0, Ft = 0.0;
+            if (wm > 0.0) {
+                Fn = q * (CL * wt + CD * wn) / wm;
+                Ft = q * (CL * wn - CD * wt) / wm;
+            }
+            const double Fp[3] = {Fn, -Ft * st, Ft * ct};
+            // Gaussian normalisation over the 13 nodes per axis (separable)
+            int c0[3];
+            double S = 1.0;
+            for (int ax = 0; ax < 3; ++ax) {
+                c0[ax] = (int)floor(xp[ax] + 0.5);
+                double sa = 0.0;
+                for (int d = -SUPPORT; d <= SUPPORT; ++d) {
+                    const double e = (c0[ax] + d) - xp[ax];
+                    sa += exp(-e * e / (R.eps * R.eps));
+                }
+                S *= sa;
+            }
+            float *P = R.pts + (size_t)p * PT_STRIDE;
+            for (int ax = 0; ax < 3; ++ax) {
+                P[ax] = (float)(xp[ax] - c0[ax]);  // offset from the nearest node
+                P[3 + ax] = (float)(-Fp[ax]);
+                P[6 + ax] = (float)c0[ax];
+                R.pt_force[3 * p + ax] = Fp[ax];
+            }
+            P[9] = (float)(1.0 / S);
+            accT += Fn;
+            accQ += rr * Ft;
+        }
+        __syncthreads();
+    }
+    // deterministic FP64 tree reduction of thrust and torque
+    s_red[threadIdx.x][0] = accT;
+    s_red[threadIdx.x][1] = accQ;
+    __syncthreads();
+    for (int s = ALM_BLOCK / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            s_red[threadIdx.x][0] += s_red[threadIdx.x + s][0];
+            s_red[threadIdx.x][1] += s_red[threadIdx.x + s][1];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        R.loads[0] = s_red[0][0];
+        R.loads[1] = s_red[0][1];
+        R.loads[2] = s_red[0][1] * R.omega_rot;
+    }
+}
+
+// Gather-form spreading over one rotor's box: F(X) = sum_p (-F_p) eta(X - x_p) / W_p
+__global__ __launch_bounds__(ALM_BLOCK) void k_alm_spread(const RotorDev *rots, int rid) {
+    const RotorDev &R = rots[rid];
+    const int npts = R.n_blades * R.n_points;
+    __shared__ float sp[ALM_MAX_PTS * PT_STRIDE];
+    for (int q = threadIdx.x; q < npts * PT_STRIDE; q += ALM_BLOCK) sp[q] = R.pts[q];
+    __syncthreads();
+    const ForceBox &B = R.box;
+    const size_t nb = (size_t)B.bnx * B.bny * B.bnz;
+    const size_t c = blockIdx.x * (size_t)ALM_BLOCK + threadIdx.x;
+    if (c >= nb) return;
+    const int lx = (int)(c % B.bnx), ly = (int)((c / B.bnx) % B.bny), lz = (int)(c / ((size_t)B.bnx * B.bny));
+    const int X = B.x0 + lx, Y = B.y0 + ly, Z = B.z0 + lz;
+    const float ie2 = (float)(1.0 / (R.eps * R.eps));
+    float Fx = 0.f, Fy = 0.f, Fz = 0.f;
+    for (int p = 0; p < npts; ++p) {
+        const float *P = sp + p * PT_STRIDE;
+        const int dx = X - (int)P[6], dy = Y - (int)P[7], dz = Z - (int)P[8];
+        if (abs(dx) > SUPPORT || abs(dy) > SUPPORT || abs(dz) > SUPPORT) continue;
+        const float ex = (float)dx - P[0], ey = (float)dy - P[1], ez = (float)dz - P[2];
+        const float w = expf(-(ex * ex + ey * ey + ez * ez) * ie2) * P[9];
+        Fx = fmaf(w, P[3], Fx);
+        Fy = fmaf(w, P[4], Fy);
+        Fz = fmaf(w, P[5], Fz);
+    }
+    R.Fbox[c] = Fx;
+    R.Fbox[nb + c] = Fy;
+    R.Fbox[2 * nb + c] = Fz;
+}
+
+template <typename T, int PAR>
+static void alm_t(const Geo &g, const Physics &ph, const RotorDev *h_rots, RotorDev *d_rots, int nrot, long t,
+                  hipStream_t s) {
+    k_alm_points<T, PAR><<<nrot, ALM_BLOCK, 0, s>>>(g, ph, d_rots, t);
+    for (int r = 0; r < nrot; ++r) {
+        const size_t nb = (size_t)h_rots[r].box.bnx * h_rots[r].box.bny * h_rots[r].box.bnz;
+        k_alm_spread<<<(unsigned)((nb + ALM_BLOCK - 1) / ALM_BLOCK), ALM_BLOCK, 0, s>>>(d_rots, r);
+    }
+}
+
+int launch_alm(int storage, int parity, const Geo &g, const Physics &ph, const RotorDev *h_rots, RotorDev *d_rots,
+               int nrot, long t, hipStream_t s) {
+    switch (storage * 2 + parity) {
+        case 0: alm_t<float, 0>(g, ph, h_rots, d_rots, nrot, t, s); break;
+        case 1: alm_t<float, 1>(g, ph, h_rots, d_rots, nrot, t, s); break;
+        case 2: alm_t<__half, 0>(g, ph, h_rots, d_rots, nrot, t, s); break;
+        case 3: alm_t<__half, 1>(g, ph, h_rots, d_rots, nrot, t, s); break;
+        case 4: alm_t<bf16_t, 0>(g, ph, h_rots, d_rots, nrot, t, s); break;
+        case 5: alm_t<bf16_t, 1>(g, ph, h_rots, d_rots, nrot, t, s); break;
+        default: return -1;
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+}  // namespace lbm

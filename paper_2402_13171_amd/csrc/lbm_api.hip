@@ -1,0 +1,601 @@
+// Host side of the C ABI declared in include/lbm.h: argument validation,
+// device bookkeeping and the per-step kernel sequence.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "lbm_internal.h"
+
+using namespace lbm;
+
+namespace {
+
+struct RotorHost {
+    bool on = false;
+    RotorDev dev{};  // host copy of the device description (device pointers inside)
+    int npts = 0;
+    double *d_r = nullptr, *d_chord = nullptr, *d_twist = nullptr, *d_dl = nullptr;
+    float *d_cl = nullptr, *d_cd = nullptr, *d_pts = nullptr, *d_Fbox = nullptr;
+    double *d_ptf = nullptr, *d_loads = nullptr;
+};
+
+size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+}  // namespace
+
+struct lbm_ctx {
+    lbm_config cfg{};
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    size_t n = 0, P = 0, esize = 4;
+    size_t pop_bytes = 0, aux_bytes = 0;
+    size_t off_ghost = 0, off_uin = 0, off_part = 0, off_flag = 0;
+    void *pops = nullptr, *aux = nullptr;
+    bool attached = false;
+    long t = 0;
+    int parity = 0;
+    float omega2 = 1.0f;
+    float *d_ffield = nullptr;
+    RotorHost rot[MAX_ROTORS];
+    RotorDev *d_rots = nullptr;  // compacted active rotors
+    std::vector<RotorDev> h_rots;
+    MlpDev *d_mlp = nullptr;
+    bool mlp_set = false;
+    double mass0 = 0.0;
+    bool mass0_set = false;
+    double *d_stage = nullptr;
+    size_t stage_bytes = 0;
+    std::string err;
+};
+
+namespace {
+
+int fail(lbm_ctx *c, int code, const char *fmt, ...) {
+    if (c) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        c->err = buf;
+    }
+    return code;
+}
+
+#define HIPCHK(ctx, expr)                                                                         \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess) return fail(ctx, LBM_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+Geo geo_of(const lbm_ctx *c) {
+    Geo g{};
+    g.pops = c->pops;
+    g.P = c->P;
+    g.nx = c->cfg.nx;
+    g.ny = c->cfg.ny;
+    g.nz = c->cfg.nz;
+    g.bc_x = c->cfg.bc_x;
+    g.bc_zlo = c->cfg.bc_z_lo;
+    g.bc_zhi = c->cfg.bc_z_hi;
+    g.uin = (const float *)((char *)c->aux + c->off_uin);
+    g.ghost = (char *)c->aux + c->off_ghost;
+    return g;
+}
+
+bool has_force(const lbm_ctx *c) {
+    return c->cfg.body_force[0] != 0.0 || c->cfg.body_force[1] != 0.0 || c->cfg.body_force[2] != 0.0 ||
+           c->d_ffield != nullptr || !c->h_rots.empty();
+}
+
+Physics physics_of(const lbm_ctx *c) {
+    Physics ph{};
+    ph.omega = (float)c->cfg.omega;
+    ph.omega2 = c->omega2;
+    ph.tau0 = (float)(1.0 / c->cfg.omega);
+    ph.smag_c = (float)(18.0 * std::sqrt(2.0) * c->cfg.cs_smag * c->cfg.cs_smag);
+    ph.nu0 = (float)((1.0 / c->cfg.omega - 0.5) / 3.0);
+    for (int k = 0; k < 3; ++k) ph.bf[k] = (float)c->cfg.body_force[k];
+    ph.ffield = c->d_ffield;
+    ph.nbox = (int)c->h_rots.size();
+    for (int r = 0; r < ph.nbox; ++r) ph.box[r] = c->h_rots[r].box;
+    ph.mlp = c->d_mlp;
+    return ph;
+}
+
+bool general_bc(const lbm_ctx *c) {
+    return c->cfg.bc_x != LBM_BC_PERIODIC || c->cfg.bc_z_lo != LBM_BC_PERIODIC || c->cfg.bc_z_hi != LBM_BC_PERIODIC;
+}
+
+int ensure_stage(lbm_ctx *c, size_t bytes) {
+    if (c->stage_bytes >= bytes) return LBM_OK;
+    if (c->d_stage) (void)hipFree(c->d_stage);
+    c->d_stage = nullptr;
+    c->stage_bytes = 0;
+    if (hipMalloc((void **)&c->d_stage, bytes) != hipSuccess) return fail(c, LBM_ENOMEM, "staging buffer of %zu bytes", bytes);
+    c->stage_bytes = bytes;
+    return LBM_OK;
+}
+
+// cells per host<->device chunk (keeps the staging buffer modest)
+size_t chunk_cells(const lbm_ctx *c) {
+    const size_t target = (size_t)1 << 22;
+    return c->n < target ? c->n : target;
+}
+
+int ready(lbm_ctx *c) {
+    if (!c) return LBM_EINVAL;
+    if (!c->attached) return fail(c, LBM_ESTATE, "call lbm_attach first");
+    return LBM_OK;
+}
+
+int refresh_rotor_table(lbm_ctx *c) {
+    c->h_rots.clear();
+    for (int r = 0; r < MAX_ROTORS; ++r)
+        if (c->rot[r].on) c->h_rots.push_back(c->rot[r].dev);
+    if (c->h_rots.empty()) return LBM_OK;
+    if (!c->d_rots) {
+        if (hipMalloc((void **)&c->d_rots, sizeof(RotorDev) * MAX_ROTORS) != hipSuccess)
+            return fail(c, LBM_ENOMEM, "rotor table");
+    }
+    HIPCHK(c, hipMemcpyAsync(c->d_rots, c->h_rots.data(), sizeof(RotorDev) * c->h_rots.size(),
+                             hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+void free_rotor(RotorHost &R) {
+    void *ptrs[] = {R.d_r, R.d_chord, R.d_twist, R.d_dl, R.d_cl, R.d_cd, R.d_pts, R.d_Fbox, R.d_ptf, R.d_loads};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    R = RotorHost{};
+}
+
+int zero_rotor_boxes(lbm_ctx *c) {
+    for (int r = 0; r < MAX_ROTORS; ++r) {
+        RotorHost &R = c->rot[r];
+        if (!R.on) continue;
+        const size_t nb = (size_t)R.dev.box.bnx * R.dev.box.bny * R.dev.box.bnz;
+        HIPCHK(c, hipMemsetAsync(R.d_Fbox, 0, 3 * nb * sizeof(float), c->stream));
+        HIPCHK(c, hipMemsetAsync(R.d_loads, 0, 3 * sizeof(double), c->stream));
+        HIPCHK(c, hipMemsetAsync(R.d_ptf, 0, 3 * (size_t)R.npts * sizeof(double), c->stream));
+    }
+    return LBM_OK;
+}
+
+int after_init(lbm_ctx *c) {
+    c->t = 0;
+    c->parity = 0;
+    c->mass0_set = false;
+    int rc = zero_rotor_boxes(c);
+    if (rc) return rc;
+    HIPCHK(c, hipMemsetAsync((char *)c->aux + c->off_ghost, 0, c->off_uin - c->off_ghost, c->stream));
+    return LBM_OK;
+}
+
+int moments_now(lbm_ctx *c, double out[RED_NMOM]) {
+    Geo g = geo_of(c);
+    Physics ph = physics_of(c);
+    double *part = (double *)((char *)c->aux + c->off_part);
+    double *res = part + (size_t)RED_NBLOCKS * RED_NMOM;
+    if (launch_moments((int)c->cfg.storage, c->parity, g, ph, part, RED_NBLOCKS, res, c->stream))
+        return fail(c, LBM_EHIP, "moment reduction launch failed");
+    HIPCHK(c, hipMemcpyAsync(out, res, RED_NMOM * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *lbm_strerror(int code) {
+    switch (code) {
+        case LBM_OK: return "ok";
+        case LBM_EINVAL: return "invalid argument";
+        case LBM_ENOMEM: return "out of memory";
+        case LBM_EHIP: return "HIP runtime error";
+        case LBM_EUNSTABLE: return "simulation unstable (mass or NaN check failed)";
+        case LBM_ESTATE: return "call out of order";
+        default: return "unknown error";
+    }
+}
+
+const char *lbm_last_error(const lbm_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int lbm_create(const lbm_config *cfg, lbm_ctx **out) {
+    if (!cfg || !out) return LBM_EINVAL;
+    *out = nullptr;
+    const lbm_config &c = *cfg;
+    if (c.nx < 2 || c.ny < 2 || c.nz < 2) return LBM_EINVAL;
+    const size_t n = (size_t)c.nx * c.ny * c.nz;
+    if (n >= ((size_t)1 << 32)) return LBM_EINVAL;
+    if (!(c.omega > 0.0 && c.omega < 2.0)) return LBM_EINVAL;
+    for (int k = 0; k < 9; ++k)
+        if (!(c.omega_hi[k] >= 0.0 && c.omega_hi[k] < 2.0)) return LBM_EINVAL;
+    for (int k = 1; k < 9; ++k)  // omega_3..omega_10: the device collision assumes the default 1
+        if (c.omega_hi[k] != 0.0 && c.omega_hi[k] != 1.0) return LBM_EINVAL;
+    if (c.storage < LBM_F32 || c.storage > LBM_BF16) return LBM_EINVAL;
+    if (c.closure < LBM_CLOSURE_NONE || c.closure > LBM_CLOSURE_MLP) return LBM_EINVAL;
+    if (c.closure == LBM_CLOSURE_SMAG && !(c.cs_smag >= 0.0)) return LBM_EINVAL;
+    if (c.bc_x != LBM_BC_PERIODIC && c.bc_x != LBM_BC_INFLOW_OUTFLOW) return LBM_EINVAL;
+    for (int b : {c.bc_z_lo, c.bc_z_hi})
+        if (b != LBM_BC_PERIODIC && b != LBM_BC_NOSLIP && b != LBM_BC_FREESLIP) return LBM_EINVAL;
+    if ((c.bc_z_lo == LBM_BC_PERIODIC) != (c.bc_z_hi == LBM_BC_PERIODIC)) return LBM_EINVAL;
+    if (c.check_every < 0) return LBM_EINVAL;
+
+    lbm_ctx *x = new (std::nothrow) lbm_ctx();
+    if (!x) return LBM_ENOMEM;
+    x->cfg = c;
+    x->n = n;
+    x->esize = c.storage == LBM_F32 ? 4 : 2;
+    x->P = round_up(n * x->esize, 256) / x->esize;
+    x->pop_bytes = 27 * x->P * x->esize;
+    x->omega2 = c.omega_hi[0] == 0.0 ? 1.0f : (float)c.omega_hi[0];
+    const size_t plane = (size_t)c.ny * c.nz;
+    x->off_ghost = 0;
+    x->off_uin = round_up(9 * plane * x->esize, 256);
+    x->off_part = x->off_uin + round_up(3 * plane * sizeof(float), 256);
+    x->off_flag = x->off_part + round_up(((size_t)RED_NBLOCKS + 2) * RED_NMOM * sizeof(double), 256);
+    x->aux_bytes = x->off_flag + 256;
+    if (c.stream) {
+        x->stream = (hipStream_t)c.stream;
+    } else {
+        if (hipStreamCreate(&x->stream) != hipSuccess) {
+            delete x;
+            return LBM_EHIP;
+        }
+        x->own_stream = true;
+    }
+    *out = x;
+    return LBM_OK;
+}
+
+int lbm_destroy(lbm_ctx *c) {
+    if (!c) return LBM_EINVAL;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (int r = 0; r < MAX_ROTORS; ++r) free_rotor(c->rot[r]);
+    if (c->d_rots) (void)hipFree(c->d_rots);
+    if (c->d_ffield) (void)hipFree(c->d_ffield);
+    if (c->d_mlp) (void)hipFree(c->d_mlp);
+    if (c->d_stage) (void)hipFree(c->d_stage);
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+    return LBM_OK;
+}
+
+int lbm_required_bytes(const lbm_ctx *c, size_t *pop_bytes, size_t *aux_bytes) {
+    if (!c || !pop_bytes || !aux_bytes) return LBM_EINVAL;
+    *pop_bytes = c->pop_bytes;
+    *aux_bytes = c->aux_bytes;
+    return LBM_OK;
+}
+
+int lbm_attach(lbm_ctx *c, void *d_pops, void *d_aux) {
+    if (!c) return LBM_EINVAL;
+    if (!d_pops || !d_aux) return fail(c, LBM_EINVAL, "null device buffer");
+    if (((uintptr_t)d_pops & 255) || ((uintptr_t)d_aux & 255)) return fail(c, LBM_EINVAL, "buffers must be 256-byte aligned");
+    c->pops = d_pops;
+    c->aux = d_aux;
+    c->attached = true;
+    HIPCHK(c, hipMemsetAsync(d_aux, 0, c->aux_bytes, c->stream));
+    // uniform inlet plane
+    const size_t plane = (size_t)c->cfg.ny * c->cfg.nz;
+    std::vector<float> uin(3 * plane);
+    for (int d = 0; d < 3; ++d)
+        for (size_t q = 0; q < plane; ++q) uin[d * plane + q] = (float)c->cfg.u_in[d];
+    HIPCHK(c, hipMemcpyAsync((char *)d_aux + c->off_uin, uin.data(), uin.size() * sizeof(float), hipMemcpyHostToDevice,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+int lbm_init_tgv(lbm_ctx *c, double u0, double k, double rho0) {
+    int rc = ready(c);
+    if (rc) return rc;
+    if (!(rho0 > 0.0) || !std::isfinite(u0) || !std::isfinite(k)) return fail(c, LBM_EINVAL, "bad TGV parameters");
+    if (launch_init_tgv((int)c->cfg.storage, geo_of(c), u0, k, rho0, c->stream)) return fail(c, LBM_EHIP, "init launch");
+    return after_init(c);
+}
+
+int lbm_init_fields(lbm_ctx *c, const double *rho, const double *u) {
+    int rc = ready(c);
+    if (rc) return rc;
+    if (!rho || !u) return fail(c, LBM_EINVAL, "null field");
+    const size_t ch = chunk_cells(c);
+    if ((rc = ensure_stage(c, 4 * ch * sizeof(double)))) return rc;
+    Geo g = geo_of(c);
+    for (size_t c0 = 0; c0 < c->n; c0 += ch) {
+        const size_t m = c->n - c0 < ch ? c->n - c0 : ch;
+        HIPCHK(c, hipMemcpyAsync(c->d_stage, rho + c0, m * sizeof(double), hipMemcpyHostToDevice, c->stream));
+        for (int d = 0; d < 3; ++d)
+            HIPCHK(c, hipMemcpyAsync(c->d_stage + m * (1 + d), u + d * c->n + c0, m * sizeof(double),
+                                     hipMemcpyHostToDevice, c->stream));
+        if (launch_init_eq((int)c->cfg.storage, g, c->d_stage, c->d_stage + m, c0, m, c->stream))
+            return fail(c, LBM_EHIP, "init launch");
+    }
+    rc = after_init(c);
+    if (rc) return rc;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+int lbm_set_rotor(lbm_ctx *c, int id, const lbm_rotor *r) {
+    if (!c) return LBM_EINVAL;
+    if (id < 0 || id >= MAX_ROTORS || !r) return fail(c, LBM_EINVAL, "bad rotor id or null rotor");
+    if (r->axis[0] != 1.0 || r->axis[1] != 0.0 || r->axis[2] != 0.0)
+        return fail(c, LBM_EINVAL, "rotor axis must be +x");
+    if (r->n_blades < 1 || r->n_points < 1 || r->n_blades * r->n_points > ALM_MAX_POINTS)
+        return fail(c, LBM_EINVAL, "n_blades*n_points must be in [1, %d]", ALM_MAX_POINTS);
+    if (r->n_polar < 2 || !r->r || !r->chord || !r->twist_deg || !r->dl || !r->alpha_deg || !r->cl || !r->cd)
+        return fail(c, LBM_EINVAL, "missing rotor arrays");
+    if (!(r->eps > 0.0) || !(r->radius > 0.0)) return fail(c, LBM_EINVAL, "eps and radius must be positive");
+    const double a0 = r->alpha_deg[0], da = (r->alpha_deg[r->n_polar - 1] - a0) / (r->n_polar - 1);
+    if (!(da > 0.0)) return fail(c, LBM_EINVAL, "polar angles must ascend");
+    for (int k = 0; k < r->n_polar; ++k)
+        if (std::fabs(r->alpha_deg[k] - (a0 + k * da)) > 1e-9 * (1.0 + std::fabs(a0)))
+            return fail(c, LBM_EINVAL, "polar angle grid must be uniform");
+    double rmax = 0.0;
+    for (int k = 0; k < r->n_points; ++k) {
+        rmax = std::fmax(rmax, std::fabs(r->r[k]));
+        if (!(std::fabs(r->twist_deg[k] + r->pitch_deg) < 180.0))
+            return fail(c, LBM_EINVAL, "|twist + pitch| must stay below 180 degrees");
+    }
+    // spreading box: every support node round(x_p) +- SUPPORT of every point
+    const int bx0 = (int)std::floor(r->hub[0] + 0.5) - SUPPORT, bx1 = (int)std::floor(r->hub[0] + 0.5) + SUPPORT;
+    const int by0 = (int)std::floor(r->hub[1] - rmax + 0.5) - SUPPORT, by1 = (int)std::floor(r->hub[1] + rmax + 0.5) + SUPPORT;
+    const int bz0 = (int)std::floor(r->hub[2] - rmax + 0.5) - SUPPORT, bz1 = (int)std::floor(r->hub[2] + rmax + 0.5) + SUPPORT;
+    if (bx0 < 0 || by0 < 0 || bz0 < 0 || bx1 >= c->cfg.nx || by1 >= c->cfg.ny || bz1 >= c->cfg.nz)
+        return fail(c, LBM_EINVAL, "rotor spreading box [%d,%d]x[%d,%d]x[%d,%d] leaves the domain", bx0, bx1, by0, by1,
+                    bz0, bz1);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    RotorHost &R = c->rot[id];
+    free_rotor(R);
+    const int np = r->n_points, npts = r->n_blades * np, nb = (bx1 - bx0 + 1) * (by1 - by0 + 1) * (bz1 - bz0 + 1);
+    bool ok = hipMalloc((void **)&R.d_r, np * sizeof(double)) == hipSuccess &&
+              hipMalloc((void **)&R.d_chord, np * sizeof(double)) == hipSuccess &&
+              hipMalloc((void **)&R.d_twist, np * sizeof(double)) == hipSuccess &&
+              hipMalloc((void **)&R.d_dl, np * sizeof(double)) == hipSuccess &&
+              hipMalloc((void **)&R.d_cl, r->n_polar * sizeof(float)) == hipSuccess &&
+              hipMalloc((void **)&R.d_cd, r->n_polar * sizeof(float)) == hipSuccess &&
+              hipMalloc((void **)&R.d_pts, (size_t)npts * PT_STRIDE * sizeof(float)) == hipSuccess &&
+              hipMalloc((void **)&R.d_ptf, (size_t)npts * 3 * sizeof(double)) == hipSuccess &&
+              hipMalloc((void **)&R.d_loads, 3 * sizeof(double)) == hipSuccess &&
+              hipMalloc((void **)&R.d_Fbox, (size_t)nb * 3 * sizeof(float)) == hipSuccess;
+    if (!ok) {
+        free_rotor(R);
+        return fail(c, LBM_ENOMEM, "rotor buffers");
+    }
+    std::vector<float> cl(r->n_polar), cd(r->n_polar);
+    for (int k = 0; k < r->n_polar; ++k) {
+        cl[k] = (float)r->cl[k];
+        cd[k] = (float)r->cd[k];
+    }
+    HIPCHK(c, hipMemcpy(R.d_r, r->r, np * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(R.d_chord, r->chord, np * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(R.d_twist, r->twist_deg, np * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(R.d_dl, r->dl, np * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(R.d_cl, cl.data(), r->n_polar * sizeof(float), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(R.d_cd, cd.data(), r->n_polar * sizeof(float), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemset(R.d_Fbox, 0, (size_t)nb * 3 * sizeof(float)));
+    HIPCHK(c, hipMemset(R.d_loads, 0, 3 * sizeof(double)));
+    HIPCHK(c, hipMemset(R.d_ptf, 0, (size_t)npts * 3 * sizeof(double)));
+    RotorDev &D = R.dev;
+    D = RotorDev{};
+    for (int k = 0; k < 3; ++k) D.hub[k] = r->hub[k];
+    D.omega_rot = r->omega_rot;
+    D.azimuth0 = r->azimuth0;
+    D.pitch_deg = r->pitch_deg;
+    D.eps = r->eps;
+    D.n_blades = r->n_blades;
+    D.n_points = np;
+    D.n_polar = r->n_polar;
+    D.alpha0 = a0;
+    D.dalpha = da;
+    D.r = R.d_r;
+    D.chord = R.d_chord;
+    D.twist = R.d_twist;
+    D.dl = R.d_dl;
+    D.cl = R.d_cl;
+    D.cd = R.d_cd;
+    D.pts = R.d_pts;
+    D.pt_force = R.d_ptf;
+    D.loads = R.d_loads;
+    D.box = ForceBox{bx0, by0, bz0, bx1 - bx0 + 1, by1 - by0 + 1, bz1 - bz0 + 1, R.d_Fbox};
+    D.Fbox = R.d_Fbox;
+    R.npts = npts;
+    R.on = true;
+    return refresh_rotor_table(c);
+}
+
+int lbm_step(lbm_ctx *c, int nsteps) {
+    int rc = ready(c);
+    if (rc) return rc;
+    if (nsteps < 0) return fail(c, LBM_EINVAL, "negative step count");
+    if (c->cfg.closure == LBM_CLOSURE_MLP && !c->mlp_set) return fail(c, LBM_ESTATE, "closure weights not set");
+    const int st = (int)c->cfg.storage;
+    const bool bcg = general_bc(c);
+    int *flag = (int *)((char *)c->aux + c->off_flag);
+    double *part = (double *)((char *)c->aux + c->off_part);
+    const double tol = 1e-6;
+    if (c->cfg.check_every > 0 && !c->mass0_set) {
+        double m[RED_NMOM];
+        if ((rc = moments_now(c, m))) return rc;
+        c->mass0 = m[0];
+        c->mass0_set = true;
+        HIPCHK(c, hipMemsetAsync(flag, 0, sizeof(int), c->stream));
+    }
+    Geo g = geo_of(c);
+    const int nrot = (int)c->h_rots.size();
+    for (int s = 0; s < nsteps; ++s) {
+        Physics ph = physics_of(c);
+        const bool frc = has_force(c);
+        if (nrot > 0 && launch_alm(st, c->parity, g, ph, c->h_rots.data(), c->d_rots, nrot, c->t, c->stream))
+            return fail(c, LBM_EHIP, "actuator-line launch failed");
+        if (launch_stream_collide(st, c->parity, (int)c->cfg.closure, bcg, frc, g, ph, c->stream))
+            return fail(c, LBM_EHIP, "stream-collide launch failed");
+        c->parity ^= 1;
+        c->t += 1;
+        if (c->cfg.check_every > 0 && (c->t % c->cfg.check_every == 0 || s == nsteps - 1)) {
+            if (launch_check(st, c->parity, g, ph, part, RED_NBLOCKS, c->mass0, tol, flag, c->stream))
+                return fail(c, LBM_EHIP, "check launch failed");
+        }
+    }
+    if (c->cfg.check_every > 0) {
+        int h = 0;
+        HIPCHK(c, hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        if (h) return fail(c, LBM_EUNSTABLE, "mass drift above %g or NaN detected", tol);
+    }
+    return LBM_OK;
+}
+
+int lbm_get_fields(lbm_ctx *c, double *rho, double *u) {
+    int rc = ready(c);
+    if (rc) return rc;
+    if (!rho || !u) return fail(c, LBM_EINVAL, "null output");
+    const size_t ch = chunk_cells(c);
+    if ((rc = ensure_stage(c, 4 * ch * sizeof(double)))) return rc;
+    Geo g = geo_of(c);
+    Physics ph = physics_of(c);
+    for (size_t c0 = 0; c0 < c->n; c0 += ch) {
+        const size_t m = c->n - c0 < ch ? c->n - c0 : ch;
+        if (launch_fields((int)c->cfg.storage, c->parity, g, ph, c->d_stage, c->d_stage + m, c0, m, c->stream))
+            return fail(c, LBM_EHIP, "field launch");
+        HIPCHK(c, hipMemcpyAsync(rho + c0, c->d_stage, m * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        for (int d = 0; d < 3; ++d)
+            HIPCHK(c, hipMemcpyAsync(u + d * c->n + c0, c->d_stage + m * (1 + d), m * sizeof(double),
+                                     hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    return LBM_OK;
+}
+
+int lbm_get_pops(lbm_ctx *c, double *f) {
+    int rc = ready(c);
+    if (rc) return rc;
+    if (!f) return fail(c, LBM_EINVAL, "null output");
+    const size_t ch = chunk_cells(c) / 8 > 0 ? chunk_cells(c) / 8 : 1;
+    if ((rc = ensure_stage(c, 27 * ch * sizeof(double)))) return rc;
+    Geo g = geo_of(c);
+    for (size_t c0 = 0; c0 < c->n; c0 += ch) {
+        const size_t m = c->n - c0 < ch ? c->n - c0 : ch;
+        if (launch_pops((int)c->cfg.storage, c->parity, g, c->d_stage, c0, m, c->stream))
+            return fail(c, LBM_EHIP, "population launch");
+        for (int i = 0; i < 27; ++i)
+            HIPCHK(c, hipMemcpyAsync(f + (size_t)i * c->n + c0, c->d_stage + (size_t)i * m, m * sizeof(double),
+                                     hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    return LBM_OK;
+}
+
+int lbm_rotor_loads(lbm_ctx *c, int id, double out[3], double *pt_force) {
+    int rc = ready(c);
+    if (rc) return rc;
+    if (id < 0 || id >= MAX_ROTORS || !out) return fail(c, LBM_EINVAL, "bad rotor id or null output");
+    RotorHost &R = c->rot[id];
+    if (!R.on) return fail(c, LBM_EINVAL, "rotor %d not set", id);
+    HIPCHK(c, hipMemcpyAsync(out, R.d_loads, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    if (pt_force)
+        HIPCHK(c, hipMemcpyAsync(pt_force, R.d_ptf, 3 * (size_t)R.npts * sizeof(double), hipMemcpyDeviceToHost,
+                                 c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+int lbm_global_moments(lbm_ctx *c, double *mass, double mom[3], double *ke) {
+    int rc = ready(c);
+    if (rc) return rc;
+    if (!mass || !mom || !ke) return fail(c, LBM_EINVAL, "null output");
+    double m[RED_NMOM];
+    if ((rc = moments_now(c, m))) return rc;
+    *mass = m[0];
+    mom[0] = m[1];
+    mom[1] = m[2];
+    mom[2] = m[3];
+    *ke = m[4];
+    return LBM_OK;
+}
+
+int lbm_time(const lbm_ctx *c, long *t) {
+    if (!c || !t) return LBM_EINVAL;
+    *t = c->t;
+    return LBM_OK;
+}
+
+int lbm_set_force_field(lbm_ctx *c, const double *F) {
+    if (!c) return LBM_EINVAL;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    if (!F) {
+        if (c->d_ffield) (void)hipFree(c->d_ffield);
+        c->d_ffield = nullptr;
+        return LBM_OK;
+    }
+    if (!c->d_ffield && hipMalloc((void **)&c->d_ffield, 3 * c->n * sizeof(float)) != hipSuccess) {
+        c->d_ffield = nullptr;
+        return fail(c, LBM_ENOMEM, "force field");
+    }
+    std::vector<float> tmp(3 * c->n);
+    for (size_t k = 0; k < 3 * c->n; ++k) tmp[k] = (float)F[k];
+    HIPCHK(c, hipMemcpy(c->d_ffield, tmp.data(), tmp.size() * sizeof(float), hipMemcpyHostToDevice));
+    return LBM_OK;
+}
+
+int lbm_set_closure_weights(lbm_ctx *c, const float *w, size_t n) {
+    if (!c) return LBM_EINVAL;
+    if (!w || n != (size_t)MLP_NBLOB) return fail(c, LBM_EINVAL, "expected %d closure parameters", MLP_NBLOB);
+    return fail(c, LBM_EINVAL, "learned closure not available in this build");
+}
+
+int lbm_state_bytes(const lbm_ctx *c, size_t *bytes) {
+    if (!c || !bytes) return LBM_EINVAL;
+    *bytes = 64 + c->pop_bytes + c->off_uin;
+    return LBM_OK;
+}
+
+int lbm_get_state(lbm_ctx *c, void *buf, size_t bytes) {
+    int rc = ready(c);
+    if (rc) return rc;
+    size_t need;
+    lbm_state_bytes(c, &need);
+    if (!buf || bytes < need) return fail(c, LBM_EINVAL, "state buffer needs %zu bytes", need);
+    char *b = (char *)buf;
+    memset(b, 0, 64);
+    const long hdr[4] = {0x4c424d31L, c->t, c->parity, (long)c->cfg.storage};
+    memcpy(b, hdr, sizeof hdr);
+    HIPCHK(c, hipMemcpyAsync(b + 64, c->pops, c->pop_bytes, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(b + 64 + c->pop_bytes, (char *)c->aux + c->off_ghost, c->off_uin, hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+int lbm_set_state(lbm_ctx *c, const void *buf, size_t bytes) {
+    int rc = ready(c);
+    if (rc) return rc;
+    size_t need;
+    lbm_state_bytes(c, &need);
+    if (!buf || bytes < need) return fail(c, LBM_EINVAL, "state buffer needs %zu bytes", need);
+    const char *b = (const char *)buf;
+    long hdr[4];
+    memcpy(hdr, b, sizeof hdr);
+    if (hdr[0] != 0x4c424d31L || hdr[3] != (long)c->cfg.storage || (hdr[2] != 0 && hdr[2] != 1))
+        return fail(c, LBM_EINVAL, "state header does not match this context");
+    HIPCHK(c, hipMemcpyAsync(c->pops, b + 64, c->pop_bytes, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync((char *)c->aux + c->off_ghost, b + 64 + c->pop_bytes, c->off_uin, hipMemcpyHostToDevice,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->t = hdr[1];
+    c->parity = (int)hdr[2];
+    c->mass0_set = false;
+    return LBM_OK;
+}
+
+}  // extern "C"

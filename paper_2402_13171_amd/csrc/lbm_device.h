@@ -1,0 +1,221 @@
+// Device-side building blocks of the D3Q27 cumulant update (gfx950).
+//
+// Populations are stored as deviations d_i = f_i - w_i from the lattice
+// weights, so every quantity the collision forms (density deviation,
+// momentum, second moments, cumulant deviations) is a small number and FP32
+// keeps its relative precision. The collision works on these deviations end
+// to end: it never rebuilds f_i = w_i + d_i.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+namespace lbm {
+
+// ------------------------------------------------------------ lattice
+__host__ __device__ constexpr int cx_of(int i) { return i % 3 - 1; }
+__host__ __device__ constexpr int cy_of(int i) { return (i / 3) % 3 - 1; }
+__host__ __device__ constexpr int cz_of(int i) { return i / 9 - 1; }
+__host__ __device__ constexpr int opp(int i) { return 26 - i; }
+__host__ __device__ constexpr int refl_z(int i) { return i - 18 * cz_of(i); }
+__host__ __device__ constexpr float w1d(int c) { return c == 0 ? 2.0f / 3.0f : 1.0f / 6.0f; }
+__host__ __device__ constexpr float wgt(int i) { return w1d(cx_of(i)) * w1d(cy_of(i)) * w1d(cz_of(i)); }
+
+// ------------------------------------------------------------ storage types
+struct bf16_t { uint16_t v; };
+
+template <typename T> struct Store;
+template <> struct Store<float> {
+    static __device__ __forceinline__ float ld(const float *p) { return *p; }
+    static __device__ __forceinline__ void st(float *p, float v) { *p = v; }
+};
+template <> struct Store<__half> {
+    static __device__ __forceinline__ float ld(const __half *p) { return __half2float(*p); }
+    static __device__ __forceinline__ void st(__half *p, float v) { *p = __float2half_rn(v); }
+};
+// bfloat16: upper half of the float32 pattern, rounded to nearest even
+__device__ __forceinline__ uint16_t f32_to_bf16_bits(float v) {
+    uint32_t b = __float_as_uint(v);
+    if ((b & 0x7f800000u) == 0x7f800000u) return (uint16_t)(b >> 16) | ((b & 0xffffu) ? 0x40u : 0u);
+    b += 0x7fffu + ((b >> 16) & 1u);
+    return (uint16_t)(b >> 16);
+}
+__device__ __forceinline__ float bf16_bits_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+template <> struct Store<bf16_t> {
+    static __device__ __forceinline__ float ld(const bf16_t *p) { return bf16_bits_to_f32(p->v); }
+    static __device__ __forceinline__ void st(bf16_t *p, float v) { p->v = f32_to_bf16_bits(v); }
+};
+
+// ------------------------------------------------------------ collision
+// Closure kinds (values match lbm_closure).
+enum { CL_NONE = 0, CL_SMAG = 1, CL_MLP = 2 };
+
+struct CellMoments {
+    float drho, rho, ux, uy, uz;
+    float ex, ey, ez;      // k_aa - 1/3, normalised diagonal second central moments
+    float kxy, kxz, kyz;   // normalised off-diagonal second central moments
+};
+
+// Density deviation, momentum and second raw moments of the deviations,
+// taken one axis at a time (z lines, then y, then x), then the velocity
+// u = (j + F/2)/rho and the normalised second central moments about u.
+__device__ __forceinline__ CellMoments moments_of(const float d[27], float Fx, float Fy, float Fz) {
+    float Z0[9], Z1[9], Z2[9];
+#pragma unroll
+    for (int p = 0; p < 9; ++p) {
+        float a = d[p], b = d[p + 9], c = d[p + 18];
+        Z0[p] = a + b + c;
+        Z1[p] = c - a;
+        Z2[p] = c + a;
+    }
+    // y pass: index p = ix + 3*iy
+    float Y00[3], Y01[3], Y02[3], Y10[3], Y11[3], Y20[3];
+#pragma unroll
+    for (int ix = 0; ix < 3; ++ix) {
+        Y00[ix] = Z0[ix] + Z0[ix + 3] + Z0[ix + 6];
+        Y01[ix] = Z0[ix + 6] - Z0[ix];
+        Y02[ix] = Z0[ix + 6] + Z0[ix];
+        Y10[ix] = Z1[ix] + Z1[ix + 3] + Z1[ix + 6];
+        Y11[ix] = Z1[ix + 6] - Z1[ix];
+        Y20[ix] = Z2[ix] + Z2[ix + 3] + Z2[ix + 6];
+    }
+    const float m000 = Y00[0] + Y00[1] + Y00[2];
+    const float m100 = Y00[2] - Y00[0];
+    const float m200 = Y00[2] + Y00[0];
+    const float m010 = Y01[0] + Y01[1] + Y01[2];
+    const float m110 = Y01[2] - Y01[0];
+    const float m020 = Y02[0] + Y02[1] + Y02[2];
+    const float m001 = Y10[0] + Y10[1] + Y10[2];
+    const float m101 = Y10[2] - Y10[0];
+    const float m011 = Y11[0] + Y11[1] + Y11[2];
+    const float m002 = Y20[0] + Y20[1] + Y20[2];
+
+    CellMoments m;
+    m.drho = m000;
+    m.rho = 1.0f + m000;
+    const float irho = 1.0f / m.rho;
+    m.ux = (m100 + 0.5f * Fx) * irho;
+    m.uy = (m010 + 0.5f * Fy) * irho;
+    m.uz = (m001 + 0.5f * Fz) * irho;
+    // kappa_ab = Pi_ab - rho u_a u_b + (u_a F_b + u_b F_a)/2, Pi_aa = m_aa + 1/3
+    // e_a = kappa_aa/rho - 1/3 = (m_aa - drho/3 - rho u_a^2 + u_a F_a) / rho
+    const float d3 = m000 * (1.0f / 3.0f);
+    m.ex = (m200 - d3 - m.rho * m.ux * m.ux + m.ux * Fx) * irho;
+    m.ey = (m020 - d3 - m.rho * m.uy * m.uy + m.uy * Fy) * irho;
+    m.ez = (m002 - d3 - m.rho * m.uz * m.uz + m.uz * Fz) * irho;
+    m.kxy = (m110 - m.rho * m.ux * m.uy + 0.5f * (m.ux * Fy + m.uy * Fx)) * irho;
+    m.kxz = (m101 - m.rho * m.ux * m.uz + 0.5f * (m.ux * Fz + m.uz * Fx)) * irho;
+    m.kyz = (m011 - m.rho * m.uy * m.uz + 0.5f * (m.uy * Fz + m.uz * Fy)) * irho;
+    return m;
+}
+
+// Norm of the deviatoric non-equilibrium stress per unit density.
+__device__ __forceinline__ float q_norm(const CellMoments &m) {
+    const float tr3 = (m.ex + m.ey + m.ez) * (1.0f / 3.0f);
+    const float a = m.ex - tr3, b = m.ey - tr3, c = m.ez - tr3;
+    return sqrtf(a * a + b * b + c * c + 2.0f * (m.kxy * m.kxy + m.kxz * m.kxz + m.kyz * m.kyz));
+}
+
+// Smagorinsky shear rate in the closed form of Hou et al. (1996):
+// tau = (tau0 + sqrt(tau0^2 + 18 sqrt(2) Cs^2 Q)) / 2.
+__device__ __forceinline__ float smag_omega(float Q, float tau0, float cs2_18sqrt2) {
+    const float tau = 0.5f * (tau0 + sqrtf(tau0 * tau0 + cs2_18sqrt2 * Q));
+    return 1.0f / tau;
+}
+
+// One 1-D inverse pass on a triple of central moments (k0,k1,k2) about u:
+// raw moments m0 = k0, m1 = k1 + u k0, m2 = k2 + 2 u k1 + u^2 k0, then the
+// populations f- = (m2 - m1)/2, f0 = m0 - m2, f+ = (m2 + m1)/2.
+__device__ __forceinline__ void inv_triple(float &a, float &b, float &c, float u) {
+    const float k0 = a, k1 = b, k2 = c;
+    const float m1 = fmaf(u, k0, k1);
+    const float m2 = fmaf(u, k1 + m1, k2);
+    a = 0.5f * (m2 - m1);
+    b = k0 - m2;
+    c = 0.5f * (m2 + m1);
+}
+
+// Post-collision deviations d*_i = f*_i - w_i, for unit higher-order rates
+// (omega_3..omega_10 = 1; omega_2 arbitrary): the third- to sixth-order
+// cumulants are zero after the collision, so the post-collision central
+// moments follow from the relaxed second-order ones alone. The target array
+// is dk = kappa* - kappa_w(u), where kappa_w(u) are the central moments of
+// the weights about u (the product of 1, -u, 1/3 + u^2 per axis); the
+// inverse transform of dk is exactly f* - w.
+__device__ __forceinline__ void collide_unit_rates(const CellMoments &m, float omega1, float omega2,
+                                                   float Fx, float Fy, float Fz, float out[27]) {
+    const float r = m.rho, dr = m.drho;
+    const float ux = m.ux, uy = m.uy, uz = m.uz;
+    const float ux2 = ux * ux, uy2 = uy * uy, uz2 = uz * uz;
+    const float s1 = 1.0f - omega1;
+    // second order
+    const float dxy = s1 * (m.ex - m.ey);
+    const float dxz = s1 * (m.ex - m.ez);
+    const float trd = (1.0f - omega2) * (m.ex + m.ey + m.ez);
+    const float ex = (trd + dxy + dxz) * (1.0f / 3.0f);
+    const float ey = (trd - 2.0f * dxy + dxz) * (1.0f / 3.0f);
+    const float ez = (trd + dxy - 2.0f * dxz) * (1.0f / 3.0f);
+    const float kxy = s1 * m.kxy, kxz = s1 * m.kxz, kyz = s1 * m.kyz;
+    const float Kxx = (1.0f / 3.0f) + ex, Kyy = (1.0f / 3.0f) + ey, Kzz = (1.0f / 3.0f) + ez;
+    const float px = (1.0f / 3.0f) + ux2, py = (1.0f / 3.0f) + uy2, pz = (1.0f / 3.0f) + uz2;
+
+    float k[27];
+#define K(a, b, c) k[(a) + 3 * (b) + 9 * (c)]
+    K(0, 0, 0) = dr;
+    K(1, 0, 0) = 0.5f * Fx + ux;
+    K(0, 1, 0) = 0.5f * Fy + uy;
+    K(0, 0, 1) = 0.5f * Fz + uz;
+    K(2, 0, 0) = dr * (1.0f / 3.0f) + r * ex - ux2;
+    K(0, 2, 0) = dr * (1.0f / 3.0f) + r * ey - uy2;
+    K(0, 0, 2) = dr * (1.0f / 3.0f) + r * ez - uz2;
+    K(1, 1, 0) = r * kxy - ux * uy;
+    K(1, 0, 1) = r * kxz - ux * uz;
+    K(0, 1, 1) = r * kyz - uy * uz;
+    // third order: kappa* = 0
+    K(2, 1, 0) = uy * px;
+    K(2, 0, 1) = uz * px;
+    K(1, 2, 0) = ux * py;
+    K(0, 2, 1) = uz * py;
+    K(1, 0, 2) = ux * pz;
+    K(0, 1, 2) = uy * pz;
+    K(1, 1, 1) = ux * uy * uz;
+    // fourth order: kappa* = rho (K_aa K_bb + 2 k_ab^2), rho (K_aa k_bc + 2 k_ab k_ac)
+    K(2, 2, 0) = r * ((ex + ey) * (1.0f / 3.0f) + ex * ey + 2.0f * kxy * kxy) + dr * (1.0f / 9.0f) -
+                 (ux2 + uy2) * (1.0f / 3.0f) - ux2 * uy2;
+    K(2, 0, 2) = r * ((ex + ez) * (1.0f / 3.0f) + ex * ez + 2.0f * kxz * kxz) + dr * (1.0f / 9.0f) -
+                 (ux2 + uz2) * (1.0f / 3.0f) - ux2 * uz2;
+    K(0, 2, 2) = r * ((ey + ez) * (1.0f / 3.0f) + ey * ez + 2.0f * kyz * kyz) + dr * (1.0f / 9.0f) -
+                 (uy2 + uz2) * (1.0f / 3.0f) - uy2 * uz2;
+    K(2, 1, 1) = r * (Kxx * kyz + 2.0f * kxy * kxz) - px * uy * uz;
+    K(1, 2, 1) = r * (Kyy * kxz + 2.0f * kxy * kyz) - py * ux * uz;
+    K(1, 1, 2) = r * (Kzz * kxy + 2.0f * kxz * kyz) - pz * ux * uy;
+    // fifth order: kappa* = 0
+    K(2, 2, 1) = uz * px * py;
+    K(2, 1, 2) = uy * px * pz;
+    K(1, 2, 2) = ux * py * pz;
+    // sixth order: rho [Kxx Kyy Kzz + 2 (Kxx kyz^2 + Kyy kxz^2 + Kzz kxy^2) + 8 kxy kxz kyz]
+    {
+        const float se = ex + ey + ez;
+        const float see = ex * ey + ex * ez + ey * ez;
+        const float prod_dev = se * (1.0f / 9.0f) + see * (1.0f / 3.0f) + ex * ey * ez;
+        const float cross = 2.0f * (Kxx * kyz * kyz + Kyy * kxz * kxz + Kzz * kxy * kxy) + 8.0f * kxy * kxz * kyz;
+        const float su = ux2 + uy2 + uz2;
+        const float suu = ux2 * uy2 + ux2 * uz2 + uy2 * uz2;
+        K(2, 2, 2) = dr * (1.0f / 27.0f) + r * (prod_dev + cross) - su * (1.0f / 9.0f) - suu * (1.0f / 3.0f) -
+                     ux2 * uy2 * uz2;
+    }
+#undef K
+    // inverse transform: x lines, then y lines, then z lines
+#pragma unroll
+    for (int q = 0; q < 9; ++q) inv_triple(k[3 * q], k[3 * q + 1], k[3 * q + 2], ux);
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int ix = 0; ix < 3; ++ix) inv_triple(k[ix + 9 * c], k[ix + 9 * c + 3], k[ix + 9 * c + 6], uy);
+#pragma unroll
+    for (int p = 0; p < 9; ++p) inv_triple(k[p], k[p + 9], k[p + 18], uz);
+#pragma unroll
+    for (int i = 0; i < 27; ++i) out[i] = k[i];
+}
+
+}  // namespace lbm

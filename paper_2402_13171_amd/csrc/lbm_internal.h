@@ -1,0 +1,90 @@
+// Internal declarations shared by the kernels and the host library.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace lbm {
+
+constexpr int MAX_ROTORS = 8;
+constexpr int SUPPORT = 6;          // Gaussian support half-width (nodes)
+constexpr int MLP_NBLOB = 1326;
+
+enum Bc { BC_PERIODIC = 0, BC_INOUT = 1, BC_NOSLIP = 2, BC_FREESLIP = 3 };
+
+// Force box of one rotor: [3][bnx*bny*bnz] FP32, x fastest.
+struct ForceBox {
+    int x0, y0, z0, bnx, bny, bnz;
+    const float *F;
+};
+
+// Closure network in device memory: bf16 matrices in the matrix-core
+// operand order plus float32 vectors.
+struct MlpDev {
+    uint16_t W1[32 * 8];    // [out][in], inputs padded 6 -> 8 with zeros
+    uint16_t W2[32 * 32];   // [out][in]
+    float b1[32], b2[32], w3[32], b3;
+    float mu[8], inv_sigma[8];
+    float nu_scale;
+};
+
+// Everything a lattice kernel needs, passed by value.
+struct Geo {
+    void *pops;          // population store (storage type)
+    size_t P;            // plane stride in elements
+    int nx, ny, nz;
+    int bc_x, bc_zlo, bc_zhi;
+    const float *uin;    // inlet velocity plane [3][ny*nz]
+    void *ghost;         // outflow ghost plane [9][ny*nz] (storage type)
+};
+
+struct Physics {
+    float omega, omega2, tau0, smag_c;  // smag_c = 18 sqrt(2) Cs^2
+    float nu0;
+    float bf[3];                        // uniform body force
+    const float *ffield;                // dense force [3][n] or null
+    int nbox;
+    ForceBox box[MAX_ROTORS];
+    const MlpDev *mlp;
+};
+
+// Per-rotor device description used by the actuator-line kernels.
+struct RotorDev {
+    double hub[3];
+    double omega_rot, azimuth0, pitch_deg, eps;
+    int n_blades, n_points, n_polar;
+    double alpha0, dalpha;
+    const double *r, *chord, *twist, *dl;     // n_points
+    const float *cl, *cd;                     // n_polar
+    // outputs
+    float *pts;        // per point: x[3], F[3] (force on blade), c0[3] (as float), inv W
+    double *pt_force;  // per point: F[3] in FP64
+    double *loads;     // T, Q, P
+    // spreading box
+    ForceBox box;
+    float *Fbox;
+};
+
+constexpr int PT_STRIDE = 10;
+
+// Kernel launchers (defined in the .hip files).
+int launch_stream_collide(int storage, int parity, int closure, bool general_bc, bool force,
+                          const Geo &g, const Physics &ph, hipStream_t s);
+int launch_init_tgv(int storage, const Geo &g, double u0, double k, double rho0, hipStream_t s);
+int launch_init_eq(int storage, const Geo &g, const double *rho, const double *u, size_t cell0,
+                   size_t ncell, hipStream_t s);
+int launch_fields(int storage, int parity, const Geo &g, const Physics &ph, double *rho, double *u,
+                  size_t cell0, size_t ncell, hipStream_t s);
+int launch_pops(int storage, int parity, const Geo &g, double *f, size_t cell0, size_t ncell,
+                hipStream_t s);
+int launch_moments(int storage, int parity, const Geo &g, const Physics &ph, double *partials,
+                   int nblocks, double *out, hipStream_t s);
+int launch_check(int storage, int parity, const Geo &g, const Physics &ph, double *partials,
+                 int nblocks, double mass0, double tol, int *flag, hipStream_t s);
+int launch_alm(int storage, int parity, const Geo &g, const Physics &ph, const RotorDev *h_rots,
+               RotorDev *d_rots, int nrot, long t, hipStream_t s);
+constexpr int ALM_MAX_POINTS = 512;
+constexpr int RED_NBLOCKS = 1024;   // reduction grid (fixed: deterministic sums)
+constexpr int RED_NMOM = 6;
+
+}  // namespace lbm

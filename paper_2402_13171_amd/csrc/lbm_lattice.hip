@@ -1,0 +1,385 @@
+// Lattice kernels: fused AA-pattern stream-collide, initialisation, field
+// extraction and FP64 reductions.
+//
+// AA pattern (in place, one read and one write per population and step):
+//   even step: read slot i of the own cell, collide, write f*_i to slot 26-i
+//              of the own cell (no neighbour access);
+//   odd step:  read the pre-collision f_i from slot 26-i of x - c_i, collide,
+//              write f*_i to slot i of x + c_i.
+// After an even step the store is in "swapped" layout: the value f_i(x) that
+// the two-array scheme would hold after streaming is found in slot 26-i at
+// x - c_i (or given by a boundary rule). Every reader of the swapped layout
+// (odd steps, field extraction, sampling, checkpoints) uses read_swapped.
+//
+// Non-periodic boundaries (x inflow/outflow, z bounce-back or free-slip) only
+// change where an odd step reads and writes:
+//   read, source outside in z:  bounce-back -> slot i of the own cell (the
+//       even step left f*_{26-i} there); free-slip -> reflect c_z and read
+//       from the same z layer;
+//   read, source outside in x:  x = -1 -> inlet equilibrium; x = nx -> the
+//       ghost plane G written by the previous even step (reading slot 26-i at
+//       nx-1 directly would race with the cell at nx-2);
+//   write, target outside in z: bounce-back -> slot 26-i of the own cell;
+//       free-slip -> reflected slot in the same z layer;
+//   write, target outside in x: dropped;
+//   plus the slots no fluid cell pushes: at x = 0 the inlet equilibrium, at
+//   x = nx-1 a copy of the outgoing population (zero gradient).
+// Each rule mirrors the two-array pull with the same boundary readings, and
+// every slot keeps exactly one reader and one writer per step.
+#include "lbm_access.h"
+
+namespace lbm {
+
+// Slots that no fluid cell pushes in an odd step (x inflow/outflow only).
+template <typename T>
+__device__ __forceinline__ void odd_boundary_extras(const Geo &g, int x, int y, int z, const float *o) {
+    T *pops = (T *)g.pops;
+    if (x == 0) {
+        // directions entering through the inlet: f_eq(1, u_in) at the source
+#pragma unroll
+        for (int I = 2; I < 27; I += 3) {  // c_x = +1
+            const int cy = cy_of(I), cz = cz_of(I);
+            int sz = z - cz;
+            int ii = I;
+            if (cz != 0 && (sz < 0 || sz >= g.nz)) {
+                const int bc = sz < 0 ? g.bc_zlo : g.bc_zhi;
+                if (bc == BC_NOSLIP) continue;  // filled by the bounce-back push
+                if (bc == BC_FREESLIP) {
+                    ii = refl_z(I);
+                    sz = z;
+                } else {
+                    sz = wrapi(sz, g.nz);
+                }
+            }
+            const int sy = wrapi(y - cy, g.ny);
+            Store<T>::st(pops + (size_t)I * g.P + cidx(g, 0, y, z), inlet_dev(g, ii, sy, sz));
+        }
+    }
+    if (x == g.nx - 1) {
+        // directions entering through the outlet: copy of the outgoing value
+#pragma unroll
+        for (int J = 0; J < 27; J += 3) {  // c_x = -1
+            const int cy = cy_of(J), cz = cz_of(J);
+            const int ty = wrapi(y + cy, g.ny);
+            int tz = z + cz;
+            if (cz != 0 && (tz < 0 || tz >= g.nz)) {
+                const int bc = tz < 0 ? g.bc_zlo : g.bc_zhi;
+                if (bc == BC_NOSLIP) continue;
+                if (bc == BC_FREESLIP) {
+                    Store<T>::st(pops + (size_t)refl_z(J) * g.P + cidx(g, x, ty, z), o[J]);
+                    continue;
+                }
+                tz = wrapi(tz, g.nz);
+            }
+            Store<T>::st(pops + (size_t)J * g.P + cidx(g, x, ty, tz), o[J]);
+        }
+    }
+}
+
+template <typename T, int PAR, int CL, bool BCG, bool FRC>
+__global__ __launch_bounds__(256) void k_stream_collide(Geo g, Physics ph) {
+    const int x = blockIdx.x * 64 + threadIdx.x;
+    const int y = blockIdx.y * 4 + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= g.nx || y >= g.ny) return;
+    const size_t cell = cidx(g, x, y, z);
+    float d[27];
+    int xs[3];
+    size_t rows[9];
+    if (PAR == 0) {
+        Unroll<T, 0>::read_natural(g, cell, d);
+    } else if (!BCG) {
+        xs[0] = x == 0 ? g.nx - 1 : x - 1;
+        xs[1] = x;
+        xs[2] = x == g.nx - 1 ? 0 : x + 1;
+        const int ys[3] = {y == 0 ? g.ny - 1 : y - 1, y, y == g.ny - 1 ? 0 : y + 1};
+        const int zs[3] = {z == 0 ? g.nz - 1 : z - 1, z, z == g.nz - 1 ? 0 : z + 1};
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) rows[a + 3 * b] = ((size_t)zs[b] * g.ny + ys[a]) * g.nx;
+        Unroll<T, 0>::read_periodic(g, xs, rows, d);
+    } else {
+        Unroll<T, 0>::read_sw(g, x, y, z, d);
+    }
+
+    float Fx = 0.f, Fy = 0.f, Fz = 0.f;
+    if (FRC) cell_force(ph, (size_t)g.nx * g.ny * g.nz, cell, x, y, z, Fx, Fy, Fz);
+    const CellMoments m = moments_of(d, Fx, Fy, Fz);
+    const float om1 = omega1_of<CL>(m, ph);
+    float o[27];
+    collide_unit_rates(m, om1, ph.omega2, Fx, Fy, Fz, o);
+
+    if (PAR == 0) {
+        Unroll<T, 0>::write_swap_local(g, cell, o);
+        if (BCG && g.bc_x == BC_INOUT && x == g.nx - 1) {
+            T *G = (T *)g.ghost;
+#pragma unroll
+            for (int J = 0; J < 27; J += 3)
+                Store<T>::st(G + (size_t)(J / 3) * g.ny * g.nz + y + (size_t)g.ny * z, o[J]);
+        }
+    } else if (!BCG) {
+        Unroll<T, 0>::write_periodic(g, xs, rows, o);
+    } else {
+        Unroll<T, 0>::write_push(g, x, y, z, o);
+        if (g.bc_x == BC_INOUT) odd_boundary_extras<T>(g, x, y, z, o);
+    }
+}
+
+// ------------------------------------------------------------ dispatch
+template <typename T, int PAR, int CL>
+static void launch_sc(bool bcg, bool frc, const Geo &g, const Physics &ph, hipStream_t s) {
+    dim3 blk(64, 4, 1), grd((g.nx + 63) / 64, (g.ny + 3) / 4, g.nz);
+    if (bcg) {
+        if (frc) k_stream_collide<T, PAR, CL, true, true><<<grd, blk, 0, s>>>(g, ph);
+        else k_stream_collide<T, PAR, CL, true, false><<<grd, blk, 0, s>>>(g, ph);
+    } else {
+        if (frc) k_stream_collide<T, PAR, CL, false, true><<<grd, blk, 0, s>>>(g, ph);
+        else k_stream_collide<T, PAR, CL, false, false><<<grd, blk, 0, s>>>(g, ph);
+    }
+}
+
+template <typename T, int PAR>
+static int launch_sc_cl(int closure, bool bcg, bool frc, const Geo &g, const Physics &ph, hipStream_t s) {
+    switch (closure) {
+        case CL_NONE: launch_sc<T, PAR, CL_NONE>(bcg, frc, g, ph, s); return 0;
+        case CL_SMAG: launch_sc<T, PAR, CL_SMAG>(bcg, frc, g, ph, s); return 0;
+        default: return -1;
+    }
+}
+
+template <typename T>
+static int launch_sc_par(int parity, int closure, bool bcg, bool frc, const Geo &g, const Physics &ph,
+                         hipStream_t s) {
+    return parity == 0 ? launch_sc_cl<T, 0>(closure, bcg, frc, g, ph, s)
+                       : launch_sc_cl<T, 1>(closure, bcg, frc, g, ph, s);
+}
+
+int launch_stream_collide(int storage, int parity, int closure, bool general_bc, bool force, const Geo &g,
+                          const Physics &ph, hipStream_t s) {
+    int rc;
+    switch (storage) {
+        case 0: rc = launch_sc_par<float>(parity, closure, general_bc, force, g, ph, s); break;
+        case 1: rc = launch_sc_par<__half>(parity, closure, general_bc, force, g, ph, s); break;
+        case 2: rc = launch_sc_par<bf16_t>(parity, closure, general_bc, force, g, ph, s); break;
+        default: return -1;
+    }
+    if (rc) return rc;
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+// ------------------------------------------------------------ initialisation
+__device__ __forceinline__ double phi1d(int c, double u) {
+    return c == 0 ? (2.0 / 3.0 - u * u) : 0.5 * (1.0 / 3.0 + u * u + c * u);
+}
+
+template <typename T>
+__device__ __forceinline__ void store_eq(const Geo &g, size_t cell, double rho, double ux, double uy, double uz) {
+    T *pops = (T *)g.pops;
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+        const double w = (cx_of(i) == 0 ? 2.0 / 3.0 : 1.0 / 6.0) * (cy_of(i) == 0 ? 2.0 / 3.0 : 1.0 / 6.0) *
+                         (cz_of(i) == 0 ? 2.0 / 3.0 : 1.0 / 6.0);
+        const double fe = rho * phi1d(cx_of(i), ux) * phi1d(cy_of(i), uy) * phi1d(cz_of(i), uz);
+        Store<T>::st(pops + (size_t)i * g.P + cell, (float)(fe - w));
+    }
+}
+
+template <typename T>
+__global__ void k_init_tgv(Geo g, double u0, double k, double rho0) {
+    const size_t n = (size_t)g.nx * g.ny * g.nz;
+    for (size_t c = blockIdx.x * (size_t)blockDim.x + threadIdx.x; c < n; c += (size_t)gridDim.x * blockDim.x) {
+        const int x = (int)(c % g.nx), y = (int)((c / g.nx) % g.ny), z = (int)(c / ((size_t)g.nx * g.ny));
+        const double ux = u0 * sin(k * x) * cos(k * y) * cos(k * z);
+        const double uy = -u0 * cos(k * x) * sin(k * y) * cos(k * z);
+        store_eq<T>(g, c, rho0, ux, uy, 0.0);
+    }
+}
+
+template <typename T>
+__global__ void k_init_eq(Geo g, const double *rho, const double *u, size_t cell0, size_t ncell) {
+    for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < ncell; q += (size_t)gridDim.x * blockDim.x)
+        store_eq<T>(g, cell0 + q, rho[q], u[q], u[ncell + q], u[2 * ncell + q]);
+}
+
+template <typename T>
+static void init_tgv_t(const Geo &g, double u0, double k, double rho0, hipStream_t s) {
+    k_init_tgv<T><<<2048, 256, 0, s>>>(g, u0, k, rho0);
+}
+int launch_init_tgv(int storage, const Geo &g, double u0, double k, double rho0, hipStream_t s) {
+    switch (storage) {
+        case 0: init_tgv_t<float>(g, u0, k, rho0, s); break;
+        case 1: init_tgv_t<__half>(g, u0, k, rho0, s); break;
+        case 2: init_tgv_t<bf16_t>(g, u0, k, rho0, s); break;
+        default: return -1;
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+int launch_init_eq(int storage, const Geo &g, const double *rho, const double *u, size_t cell0, size_t ncell,
+                   hipStream_t s) {
+    const int nb = (int)((ncell + 255) / 256 < 4096 ? (ncell + 255) / 256 : 4096);
+    switch (storage) {
+        case 0: k_init_eq<float><<<nb, 256, 0, s>>>(g, rho, u, cell0, ncell); break;
+        case 1: k_init_eq<__half><<<nb, 256, 0, s>>>(g, rho, u, cell0, ncell); break;
+        case 2: k_init_eq<bf16_t><<<nb, 256, 0, s>>>(g, rho, u, cell0, ncell); break;
+        default: return -1;
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+template <typename T, int PAR>
+__global__ void k_fields(Geo g, Physics ph, double *rho, double *u, size_t cell0, size_t ncell) {
+    for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < ncell; q += (size_t)gridDim.x * blockDim.x) {
+        const size_t c = cell0 + q;
+        const int x = (int)(c % g.nx), y = (int)((c / g.nx) % g.ny), z = (int)(c / ((size_t)g.nx * g.ny));
+        double r, ux, uy, uz;
+        cell_macro<T, PAR>(g, ph, c, x, y, z, r, ux, uy, uz);
+        rho[q] = r;
+        u[q] = ux;
+        u[ncell + q] = uy;
+        u[2 * ncell + q] = uz;
+    }
+}
+
+template <typename T, int PAR>
+__global__ void k_pops(Geo g, double *f, size_t cell0, size_t ncell) {
+    for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < ncell; q += (size_t)gridDim.x * blockDim.x) {
+        const size_t c = cell0 + q;
+        const int x = (int)(c % g.nx), y = (int)((c / g.nx) % g.ny), z = (int)(c / ((size_t)g.nx * g.ny));
+        float d[27];
+        read_cell<T, PAR>(g, c, x, y, z, d);
+#pragma unroll
+        for (int i = 0; i < 27; ++i) {
+            const double w = (cx_of(i) == 0 ? 2.0 / 3.0 : 1.0 / 6.0) * (cy_of(i) == 0 ? 2.0 / 3.0 : 1.0 / 6.0) *
+                             (cz_of(i) == 0 ? 2.0 / 3.0 : 1.0 / 6.0);
+            f[(size_t)i * ncell + q] = w + (double)d[i];
+        }
+    }
+}
+
+template <typename T, int PAR>
+static void fields_t(const Geo &g, const Physics &ph, double *rho, double *u, size_t cell0, size_t ncell,
+                     hipStream_t s) {
+    const int nb = (int)((ncell + 255) / 256 < 4096 ? (ncell + 255) / 256 : 4096);
+    k_fields<T, PAR><<<nb, 256, 0, s>>>(g, ph, rho, u, cell0, ncell);
+}
+int launch_fields(int storage, int parity, const Geo &g, const Physics &ph, double *rho, double *u, size_t cell0,
+                  size_t ncell, hipStream_t s) {
+    switch (storage * 2 + parity) {
+        case 0: fields_t<float, 0>(g, ph, rho, u, cell0, ncell, s); break;
+        case 1: fields_t<float, 1>(g, ph, rho, u, cell0, ncell, s); break;
+        case 2: fields_t<__half, 0>(g, ph, rho, u, cell0, ncell, s); break;
+        case 3: fields_t<__half, 1>(g, ph, rho, u, cell0, ncell, s); break;
+        case 4: fields_t<bf16_t, 0>(g, ph, rho, u, cell0, ncell, s); break;
+        case 5: fields_t<bf16_t, 1>(g, ph, rho, u, cell0, ncell, s); break;
+        default: return -1;
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+template <typename T, int PAR>
+static void pops_t(const Geo &g, double *f, size_t cell0, size_t ncell, hipStream_t s) {
+    const int nb = (int)((ncell + 255) / 256 < 4096 ? (ncell + 255) / 256 : 4096);
+    k_pops<T, PAR><<<nb, 256, 0, s>>>(g, f, cell0, ncell);
+}
+int launch_pops(int storage, int parity, const Geo &g, double *f, size_t cell0, size_t ncell, hipStream_t s) {
+    switch (storage * 2 + parity) {
+        case 0: pops_t<float, 0>(g, f, cell0, ncell, s); break;
+        case 1: pops_t<float, 1>(g, f, cell0, ncell, s); break;
+        case 2: pops_t<__half, 0>(g, f, cell0, ncell, s); break;
+        case 3: pops_t<__half, 1>(g, f, cell0, ncell, s); break;
+        case 4: pops_t<bf16_t, 0>(g, f, cell0, ncell, s); break;
+        case 5: pops_t<bf16_t, 1>(g, f, cell0, ncell, s); break;
+        default: return -1;
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+// ------------------------------------------------------------ FP64 reductions
+// Two-stage deterministic sums: a fixed grid of blocks writes per-block
+// partials (tree order fixed by the block size), one block adds them in order.
+constexpr int RED_BLOCK = 256;
+constexpr int NMOM = 6;  // mass, px, py, pz, ke, nan-count
+
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int s = RED_BLOCK / 2; s > 0; s >>= 1) {
+        if (t < s) sh[t] += sh[t + s];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+template <typename T, int PAR>
+__global__ __launch_bounds__(RED_BLOCK) void k_moments_partial(Geo g, Physics ph, double *partials) {
+    __shared__ double sh[RED_BLOCK];
+    const size_t n = (size_t)g.nx * g.ny * g.nz;
+    double acc[NMOM] = {0, 0, 0, 0, 0, 0};
+    for (size_t c = blockIdx.x * (size_t)RED_BLOCK + threadIdx.x; c < n; c += (size_t)gridDim.x * RED_BLOCK) {
+        const int x = (int)(c % g.nx), y = (int)((c / g.nx) % g.ny), z = (int)(c / ((size_t)g.nx * g.ny));
+        double r, ux, uy, uz;
+        cell_macro<T, PAR>(g, ph, c, x, y, z, r, ux, uy, uz);
+        acc[0] += r;
+        acc[1] += r * ux;
+        acc[2] += r * uy;
+        acc[3] += r * uz;
+        acc[4] += 0.5 * r * (ux * ux + uy * uy + uz * uz);
+        acc[5] += (r != r || ux != ux || uy != uy || uz != uz) ? 1.0 : 0.0;
+    }
+    for (int k = 0; k < NMOM; ++k) {
+        const double s = block_sum(acc[k], sh);
+        if (threadIdx.x == 0) partials[(size_t)blockIdx.x * NMOM + k] = s;
+    }
+}
+
+__global__ __launch_bounds__(RED_BLOCK) void k_moments_final(const double *partials, int nblocks, double *out) {
+    __shared__ double sh[RED_BLOCK];
+    for (int k = 0; k < NMOM; ++k) {
+        double a = 0;
+        for (int b = threadIdx.x; b < nblocks; b += RED_BLOCK) a += partials[(size_t)b * NMOM + k];
+        const double s = block_sum(a, sh);
+        if (threadIdx.x == 0) out[k] = s;
+    }
+}
+
+__global__ void k_check(const double *mom, double mass0, double tol, int *flag) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const double m = mom[0];
+        const bool bad = mom[5] > 0.0 || !(fabs(m - mass0) <= tol * fabs(mass0));
+        if (bad) *flag = 1;
+    }
+}
+
+template <typename T, int PAR>
+static void moments_t(const Geo &g, const Physics &ph, double *partials, int nblocks, double *out, hipStream_t s) {
+    k_moments_partial<T, PAR><<<nblocks, RED_BLOCK, 0, s>>>(g, ph, partials);
+    k_moments_final<<<1, RED_BLOCK, 0, s>>>(partials, nblocks, out);
+}
+int launch_moments(int storage, int parity, const Geo &g, const Physics &ph, double *partials, int nblocks,
+                   double *out, hipStream_t s) {
+    switch (storage * 2 + parity) {
+        case 0: moments_t<float, 0>(g, ph, partials, nblocks, out, s); break;
+        case 1: moments_t<float, 1>(g, ph, partials, nblocks, out, s); break;
+        case 2: moments_t<__half, 0>(g, ph, partials, nblocks, out, s); break;
+        case 3: moments_t<__half, 1>(g, ph, partials, nblocks, out, s); break;
+        case 4: moments_t<bf16_t, 0>(g, ph, partials, nblocks, out, s); break;
+        case 5: moments_t<bf16_t, 1>(g, ph, partials, nblocks, out, s); break;
+        default: return -1;
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+int launch_check(int storage, int parity, const Geo &g, const Physics &ph, double *partials, int nblocks,
+                 double mass0, double tol, int *flag, hipStream_t s) {
+    double *out = partials + (size_t)nblocks * NMOM;
+    const int rc = launch_moments(storage, parity, g, ph, partials, nblocks, out, s);
+    if (rc) return rc;
+    k_check<<<1, 64, 0, s>>>(out, mass0, tol, flag);
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+}  // namespace lbm

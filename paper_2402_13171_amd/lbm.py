@@ -1,0 +1,257 @@
+"""ctypes binding of liblbm.so (the C ABI in include/lbm.h) and a small
+wrapper that allocates the caller-owned device buffers through PyTorch.
+
+Argument marshalling only: every step of the computation runs in the HIP
+library. If the library has not been built this module raises on first use.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+SO_PATH = os.path.join(_HERE, "liblbm.so")
+
+OK, EINVAL, ENOMEM, EHIP, EUNSTABLE, ESTATE = 0, -1, -2, -3, -4, -5
+STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
+CLOSURE = {"none": 0, "smag": 1, "mlp": 2}
+BC = {"periodic": 0, "inout": 1, "noslip": 2, "freeslip": 3}
+MLP_NBLOB = 1326
+
+EXPORTS = [
+    "lbm_create", "lbm_destroy", "lbm_required_bytes", "lbm_attach", "lbm_init_tgv",
+    "lbm_init_fields", "lbm_set_rotor", "lbm_step", "lbm_get_fields", "lbm_rotor_loads",
+    "lbm_global_moments", "lbm_get_pops", "lbm_time", "lbm_set_force_field",
+    "lbm_set_closure_weights", "lbm_state_bytes", "lbm_get_state", "lbm_set_state",
+    "lbm_strerror", "lbm_last_error",
+]
+
+
+class LbmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"lbm error {code}: {msg}")
+        self.code = code
+
+
+class Config(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
+                ("omega", C.c_double), ("omega_hi", C.c_double * 9),
+                ("storage", C.c_int), ("closure", C.c_int), ("cs_smag", C.c_double),
+                ("bc_x", C.c_int), ("bc_z_lo", C.c_int), ("bc_z_hi", C.c_int),
+                ("u_in", C.c_double * 3), ("body_force", C.c_double * 3),
+                ("check_every", C.c_int), ("stream", C.c_void_p)]
+
+
+_D = C.POINTER(C.c_double)
+
+
+class Rotor(C.Structure):
+    _fields_ = [("hub", C.c_double * 3), ("axis", C.c_double * 3),
+                ("radius", C.c_double), ("omega_rot", C.c_double), ("azimuth0", C.c_double),
+                ("eps", C.c_double), ("pitch_deg", C.c_double),
+                ("n_blades", C.c_int), ("n_points", C.c_int),
+                ("r", _D), ("chord", _D), ("twist_deg", _D), ("dl", _D),
+                ("n_polar", C.c_int), ("alpha_deg", _D), ("cl", _D), ("cd", _D)]
+
+
+_lib = None
+
+
+def lib():
+    """Load liblbm.so; raises if it is missing (no fallback path exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(SO_PATH):
+        raise RuntimeError(f"{SO_PATH} is not built; run __graft_entry__.build() "
+                           "or python paper_2402_13171_amd/build.py")
+    L = C.CDLL(SO_PATH)
+    vp, i, sz = C.c_void_p, C.c_int, C.c_size_t
+    sig = {
+        "lbm_create": [C.POINTER(Config), C.POINTER(vp)],
+        "lbm_destroy": [vp],
+        "lbm_required_bytes": [vp, C.POINTER(sz), C.POINTER(sz)],
+        "lbm_attach": [vp, vp, vp],
+        "lbm_init_tgv": [vp, C.c_double, C.c_double, C.c_double],
+        "lbm_init_fields": [vp, _D, _D],
+        "lbm_set_rotor": [vp, i, C.POINTER(Rotor)],
+        "lbm_step": [vp, i],
+        "lbm_get_fields": [vp, _D, _D],
+        "lbm_rotor_loads": [vp, i, _D, _D],
+        "lbm_global_moments": [vp, _D, _D, _D],
+        "lbm_get_pops": [vp, _D],
+        "lbm_time": [vp, C.POINTER(C.c_long)],
+        "lbm_set_force_field": [vp, _D],
+        "lbm_set_closure_weights": [vp, C.POINTER(C.c_float), sz],
+        "lbm_state_bytes": [vp, C.POINTER(sz)],
+        "lbm_get_state": [vp, vp, sz],
+        "lbm_set_state": [vp, vp, sz],
+    }
+    for name, args in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = C.c_int
+    L.lbm_strerror.argtypes = [i]
+    L.lbm_strerror.restype = C.c_char_p
+    L.lbm_last_error.argtypes = [vp]
+    L.lbm_last_error.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _p(a):
+    return a.ctypes.data_as(_D)
+
+
+class Lbm:
+    """One lattice on one GPU. Device memory comes from PyTorch; the library
+    enqueues its kernels on a torch stream owned by this object (``stream``),
+    so torch events recorded on it time the library's work."""
+
+    def __init__(self, nx, ny, nz, omega=1.9, omega_hi=None, storage="f32", closure="none",
+                 cs_smag=0.1, bc_x="periodic", bc_z=("periodic", "periodic"), u_in=(0, 0, 0),
+                 body_force=(0, 0, 0), check_every=0, device="cuda:0"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.stream = torch.cuda.Stream(device=self.device)
+        cfg = Config()
+        cfg.nx, cfg.ny, cfg.nz = nx, ny, nz
+        cfg.omega = omega
+        for k, v in enumerate(omega_hi or []):
+            cfg.omega_hi[k] = v
+        cfg.storage = STORAGE[storage]
+        cfg.closure = CLOSURE[closure]
+        cfg.cs_smag = cs_smag
+        cfg.bc_x = BC[bc_x]
+        cfg.bc_z_lo, cfg.bc_z_hi = BC[bc_z[0]], BC[bc_z[1]]
+        for k in range(3):
+            cfg.u_in[k] = u_in[k]
+            cfg.body_force[k] = body_force[k]
+        cfg.check_every = check_every
+        cfg.stream = self.stream.cuda_stream
+        self.cfg = cfg
+        self.shape = (nz, ny, nx)
+        self.n = nx * ny * nz
+        self._ctx = C.c_void_p()
+        self._check(lib().lbm_create(C.byref(cfg), C.byref(self._ctx)), ctx=False)
+        pb, ab = C.c_size_t(), C.c_size_t()
+        self._check(lib().lbm_required_bytes(self._ctx, C.byref(pb), C.byref(ab)))
+        self.pop_bytes, self.aux_bytes = pb.value, ab.value
+        with torch.cuda.device(self.device):
+            self.d_pops = torch.empty(self.pop_bytes, dtype=torch.uint8, device=self.device)
+            self.d_aux = torch.empty(self.aux_bytes, dtype=torch.uint8, device=self.device)
+        torch.cuda.synchronize(self.device)
+        self._check(lib().lbm_attach(self._ctx, C.c_void_p(self.d_pops.data_ptr()),
+                                     C.c_void_p(self.d_aux.data_ptr())))
+        self._npts = {}
+
+    # -------------------------------------------------------------- helpers
+    def _check(self, rc, ctx=True):
+        if rc != OK:
+            msg = lib().lbm_strerror(rc).decode()
+            if ctx and self._ctx:
+                detail = lib().lbm_last_error(self._ctx).decode()
+                if detail:
+                    msg += f" ({detail})"
+            raise LbmError(rc, msg)
+
+    def close(self):
+        if getattr(self, "_ctx", None) and self._ctx.value:
+            lib().lbm_destroy(self._ctx)
+            self._ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -------------------------------------------------------------- API
+    def init_tgv(self, u0=0.05, k=None, rho0=1.0):
+        k = 2 * np.pi / self.cfg.nx if k is None else k
+        self._check(lib().lbm_init_tgv(self._ctx, u0, k, rho0))
+
+    def init_fields(self, rho, u):
+        rho = _f64(np.broadcast_to(rho, self.shape)).reshape(-1)
+        u = _f64(u).reshape(3, -1)
+        self._check(lib().lbm_init_fields(self._ctx, _p(rho), _p(u)))
+
+    def set_rotor(self, rid, rot):
+        arrs = {k: _f64(rot[k]) for k in ("r", "chord", "twist_deg", "dl")}
+        pol = {k: _f64(rot["polar"][k]) for k in ("alpha_deg", "cl", "cd")}
+        d = Rotor()
+        for k in range(3):
+            d.hub[k] = rot["hub"][k]
+        d.axis[0], d.axis[1], d.axis[2] = 1.0, 0.0, 0.0
+        d.radius, d.omega_rot = rot["radius"], rot["omega_rot"]
+        d.azimuth0, d.eps = rot.get("azimuth0", 0.0), rot["eps"]
+        d.pitch_deg = rot.get("pitch_deg", 0.0)
+        d.n_blades, d.n_points = rot["n_blades"], len(arrs["r"])
+        d.r, d.chord = _p(arrs["r"]), _p(arrs["chord"])
+        d.twist_deg, d.dl = _p(arrs["twist_deg"]), _p(arrs["dl"])
+        d.n_polar = len(pol["alpha_deg"])
+        d.alpha_deg, d.cl, d.cd = _p(pol["alpha_deg"]), _p(pol["cl"]), _p(pol["cd"])
+        self._check(lib().lbm_set_rotor(self._ctx, rid, C.byref(d)))
+        self._npts[rid] = d.n_blades * d.n_points
+
+    def step(self, n=1):
+        self._check(lib().lbm_step(self._ctx, int(n)))
+
+    def fields(self):
+        rho = np.empty(self.shape)
+        u = np.empty((3,) + self.shape)
+        self._check(lib().lbm_get_fields(self._ctx, _p(rho), _p(u)))
+        return rho, u
+
+    def pops(self):
+        f = np.empty((27,) + self.shape)
+        self._check(lib().lbm_get_pops(self._ctx, _p(f)))
+        return f
+
+    def rotor_loads(self, rid, with_points=False):
+        out = np.zeros(3)
+        pf = np.zeros((self._npts[rid], 3))
+        self._check(lib().lbm_rotor_loads(self._ctx, rid, _p(out), _p(pf)))
+        return (out, pf) if with_points else out
+
+    def global_moments(self):
+        m, e = C.c_double(), C.c_double()
+        mom = np.zeros(3)
+        self._check(lib().lbm_global_moments(self._ctx, C.byref(m), _p(mom), C.byref(e)))
+        return m.value, mom, e.value
+
+    @property
+    def time(self):
+        t = C.c_long()
+        self._check(lib().lbm_time(self._ctx, C.byref(t)))
+        return t.value
+
+    def set_force_field(self, F):
+        if F is None:
+            self._check(lib().lbm_set_force_field(self._ctx, None))
+        else:
+            F = _f64(F).reshape(-1)
+            self._check(lib().lbm_set_force_field(self._ctx, _p(F)))
+
+    def set_closure_weights(self, blob):
+        w = np.ascontiguousarray(blob, dtype=np.float32)
+        self._check(lib().lbm_set_closure_weights(
+            self._ctx, w.ctypes.data_as(C.POINTER(C.c_float)), w.size))
+
+    def get_state(self):
+        nb = C.c_size_t()
+        self._check(lib().lbm_state_bytes(self._ctx, C.byref(nb)))
+        buf = np.empty(nb.value, dtype=np.uint8)
+        self._check(lib().lbm_get_state(self._ctx, C.c_void_p(buf.ctypes.data), nb.value))
+        return buf
+
+    def set_state(self, buf):
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        self._check(lib().lbm_set_state(self._ctx, C.c_void_p(buf.ctypes.data), buf.size))

@@ -1,0 +1,181 @@
+"""GPU <-> oracle parity of the fused AA-pattern stream-collide path, called
+through the C ABI. Inputs are the seeded synthetic fields of ``workloads``;
+expected values come from the FP64 oracle only."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+BCMAP = {"periodic": oracle.PERIODIC, "inout": oracle.INOUT, "noslip": oracle.NOSLIP,
+         "freeslip": oracle.FREESLIP}
+
+
+def _need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+
+
+def rel_vel_err(u, ref):
+    """max_x |u - u_ref| / max_x |u_ref| (Euclidean norm over components)"""
+    return np.linalg.norm(u - ref, axis=0).max() / np.linalg.norm(ref, axis=0).max()
+
+
+def make_pair(nx, ny, nz, omega=1.9, storage="f32", closure="none", cs=0.1, bc_x="periodic",
+              bc_z=("periodic", "periodic"), u_in=(0, 0, 0), body_force=(0, 0, 0)):
+    from paper_2402_13171_amd.lbm import Lbm
+    sim = Lbm(nx, ny, nz, omega=omega, storage=storage, closure=closure, cs_smag=cs,
+              bc_x=bc_x, bc_z=bc_z, u_in=u_in, body_force=body_force)
+    ref = oracle.Grid(nx, ny, nz, omega=omega, closure=oracle.CLOSURE_SMAG if closure == "smag" else 0,
+                      cs=cs, bc_x=BCMAP[bc_x], bc_zlo=BCMAP[bc_z[0]], bc_zhi=BCMAP[bc_z[1]],
+                      u_in=u_in, body_force=body_force)
+    return sim, ref
+
+
+def random_field(nx, ny, nz, seed, amp=0.04):
+    rng = np.random.default_rng(seed)
+    u = rng.uniform(-amp, amp, (3, nz, ny, nx))
+    rho = 1.0 + rng.uniform(-0.01, 0.01, (nz, ny, nx))
+    return rho, u
+
+
+def test_tgv64_fp32_matches_oracle_after_50_steps():
+    """Taylor-Green vortex 64^3, omega 1.9, 50 steps: max relative velocity
+    error <= 1e-5; FP64 mass conserved every step."""
+    _need_gpu()
+    n = 64
+    sim, ref = make_pair(n, n, n)
+    rho0, u0 = workloads.tgv_field(n, n, n, 0.05)
+    sim.init_tgv(0.05)
+    ref.init_fields(rho0, u0)
+    m0 = sim.global_moments()[0]
+    assert m0 == pytest.approx(n ** 3, rel=1e-12)
+    for s in range(50):
+        sim.step(1)
+        m, p, e = sim.global_moments()
+        assert abs(m - m0) <= 1e-9 * m0, s
+        assert np.abs(p).max() <= 1e-6 * n ** 3 * 0.05, s
+    ref.step(50)
+    _, u = sim.fields()
+    _, ur = ref.fields()
+    err = rel_vel_err(u, ur)
+    print(f"tgv64 fp32 50 steps: eps_max = {err:.3e}")
+    assert err <= 1e-5
+
+
+@pytest.mark.parametrize("steps", [1, 2, 7, 10])
+def test_ragged_periodic_box_populations(steps):
+    """70 x 37 x 9: ragged x tile (64 + 6) and y tile (9*4 + 1); odd and even
+    step counts exercise both AA layouts and the swapped-layout reader."""
+    _need_gpu()
+    nx, ny, nz = 70, 37, 9
+    sim, ref = make_pair(nx, ny, nz, omega=1.7)
+    rho, u = random_field(nx, ny, nz, seed=steps)
+    sim.init_fields(rho, u)
+    ref.init_fields(rho, u)
+    sim.step(steps)
+    ref.step(steps)
+    f = sim.pops()
+    fr = ref.get_pops()
+    assert np.abs(f - fr).max() <= 2e-7 * steps
+    assert sim.time == steps
+
+
+@pytest.mark.parametrize("case", [
+    dict(bc_x="inout", bc_z=("periodic", "periodic"), u_in=(0.05, 0.0, 0.0)),
+    dict(bc_x="periodic", bc_z=("noslip", "noslip"), body_force=(1e-5, 0, 0)),
+    dict(bc_x="periodic", bc_z=("freeslip", "freeslip")),
+    dict(bc_x="periodic", bc_z=("noslip", "freeslip")),
+    dict(bc_x="inout", bc_z=("noslip", "freeslip"), u_in=(0.05, 0.0, 0.0)),
+    dict(bc_x="inout", bc_z=("noslip", "noslip"), u_in=(0.04, 0.01, 0.0)),
+    dict(bc_x="inout", bc_z=("freeslip", "freeslip"), u_in=(0.05, -0.01, 0.0)),
+])
+@pytest.mark.parametrize("steps", [5, 6])
+def test_boundaries_match_oracle(case, steps):
+    _need_gpu()
+    nx, ny, nz = 20, 12, 10
+    sim, ref = make_pair(nx, ny, nz, omega=1.6, **case)
+    rho, u = random_field(nx, ny, nz, seed=3 + steps)
+    sim.init_fields(rho, u)
+    ref.init_fields(rho, u)
+    sim.step(steps)
+    ref.step(steps)
+    f = sim.pops()
+    fr = ref.get_pops()
+    err = np.abs(f - fr).max()
+    assert err <= 2e-7 * steps, (case, err)
+
+
+def test_dense_force_field_kolmogorov_step():
+    _need_gpu()
+    n = 16
+    sim, ref = make_pair(n, n, n, omega=1.2)
+    z = np.arange(n)
+    F = np.zeros((3, n, n, n))
+    F[0] = 1e-4 * np.sin(2 * np.pi * z / n)[:, None, None]
+    sim.set_force_field(F)
+    ref.set_force_field(F)
+    rho, u = random_field(n, n, n, seed=11, amp=0.01)
+    sim.init_fields(rho, u)
+    ref.init_fields(rho, u)
+    sim.step(9)
+    ref.step(9)
+    _, ug = sim.fields()
+    _, ur = ref.fields()
+    assert np.abs(ug - ur).max() <= 2e-7
+
+
+def test_smagorinsky_closure_matches_oracle():
+    _need_gpu()
+    n = 24
+    sim, ref = make_pair(n, n, n, omega=1.95, closure="smag", cs=0.1)
+    rho, u = random_field(n, n, n, seed=21, amp=0.05)
+    sim.init_fields(rho, u)
+    ref.init_fields(rho, u)
+    sim.step(8)
+    ref.step(8)
+    assert np.abs(sim.pops() - ref.get_pops()).max() <= 2e-6
+
+
+def test_checkpoint_roundtrip_is_bitwise():
+    _need_gpu()
+    n = 20
+    a, _ = make_pair(n, n, n)
+    rho, u = random_field(n, n, n, seed=5)
+    a.init_fields(rho, u)
+    a.step(7)
+    state = a.get_state()
+    a.step(6)
+    f1 = a.pops()
+    b, _ = make_pair(n, n, n)
+    b.set_state(state)
+    assert b.time == 7
+    b.step(6)
+    assert np.array_equal(b.pops(), f1)
+
+
+def test_unstable_run_is_reported():
+    """A check fires (LBM_EUNSTABLE) when the run blows up: huge velocity at
+    omega close to 2."""
+    _need_gpu()
+    from paper_2402_13171_amd.lbm import Lbm, LbmError, EUNSTABLE
+    n = 16
+    sim = Lbm(n, n, n, omega=1.999, check_every=5)
+    rng = np.random.default_rng(0)
+    sim.init_fields(np.ones((n, n, n)), rng.uniform(-0.6, 0.6, (3, n, n, n)))
+    with pytest.raises(LbmError) as ei:
+        sim.step(200)
+    assert ei.value.code == EUNSTABLE
+
+
+def test_stable_run_passes_checks():
+    _need_gpu()
+    from paper_2402_13171_amd.lbm import Lbm
+    n = 16
+    sim = Lbm(n, n, n, omega=1.9, check_every=4)
+    sim.init_tgv(0.05)
+    sim.step(20)
+    assert sim.time == 20

@@ -2,6 +2,8 @@
 fields are (3, nz, ny, nx) with components (ux, uy, uz)."""
 from __future__ import annotations
 
+import os
+
 import numpy as np
 
 
@@ -35,29 +37,47 @@ def shear_wave_field(nx, ny, nz, u0=1e-3, m=1):
 def random_phase_field(n, seed=0, k_peak=8.0, u_rms=0.03, dtype=np.float64):
     """Divergence-free random-phase field on a periodic n^3 box with shell
     spectrum E(k) ~ k^4 exp(-2 (k/k_peak)^2), scaled so that the
-    per-component rms velocity is u_rms. Returns (rho=1, u)."""
+    per-component rms velocity is u_rms. Returns (rho=1, u).
+
+    Recipe: on the half-spectrum (rfft layout, x last) draw a complex
+    Gaussian vector xi per wavenumber from default_rng(seed) (float32
+    normals: real parts of x, y, z, then imaginary parts), project it onto
+    the plane normal to k, scale by |k| exp(-(|k|/k_peak)^2), inverse-FFT."""
+    import scipy.fft as sfft
+
     rng = np.random.default_rng(seed)
-    kz = np.fft.fftfreq(n, 1.0 / n)
-    ky = np.fft.fftfreq(n, 1.0 / n)
-    kx = np.fft.rfftfreq(n, 1.0 / n)
-    KZ, KY, KX = np.meshgrid(kz, ky, kx, indexing="ij")
-    k2 = KX * KX + KY * KY + KZ * KZ
+    kz = np.fft.fftfreq(n, 1.0 / n).astype(np.float32)[:, None, None]
+    ky = np.fft.fftfreq(n, 1.0 / n).astype(np.float32)[None, :, None]
+    kx = np.fft.rfftfreq(n, 1.0 / n).astype(np.float32)[None, None, :]
+    shape = (n, n, n // 2 + 1)
+    k2 = kx * kx + ky * ky + kz * kz
     kk = np.sqrt(k2)
-    # shell spectrum E(k) ~ 4 pi k^2 |u_hat|^2 / 2  =>  |u_hat| ~ k exp(-(k/kp)^2)
-    amp = kk * np.exp(-(kk / k_peak) ** 2)
+    amp = kk * np.exp(-(kk / np.float32(k_peak)) ** 2)
     amp[0, 0, 0] = 0.0
-    shape = KX.shape
-    xi = [(rng.standard_normal(shape) + 1j * rng.standard_normal(shape)) for _ in range(3)]
-    # solenoidal projection (I - k k^T / k^2) xi
-    inv = np.where(k2 > 0, 1.0 / np.where(k2 > 0, k2, 1.0), 0.0)
-    kdx = (KX * xi[0] + KY * xi[1] + KZ * xi[2]) * inv
-    uh = [amp * (xi[0] - KX * kdx), amp * (xi[1] - KY * kdx), amp * (xi[2] - KZ * kdx)]
-    del xi, kdx
+    inv = np.where(k2 > 0, 1.0 / np.where(k2 > 0, k2, 1.0), 0.0).astype(np.float32)
+    del kk
+    xi = np.empty((3,) + shape, dtype=np.complex64)
+    for c in range(3):
+        xi[c].real = rng.standard_normal(shape, dtype=np.float32)
+    for c in range(3):
+        xi[c].imag = rng.standard_normal(shape, dtype=np.float32)
+    kdx = xi[0] * kx
+    kdx += xi[1] * ky
+    kdx += xi[2] * kz
+    kdx *= inv
+    del inv
+    for c, kc in enumerate((kx, ky, kz)):
+        xi[c] -= kc * kdx
+        xi[c] *= amp
+    del kdx, amp, k2
+    workers = os.cpu_count() or 1
     u = np.empty((3, n, n, n), dtype=dtype)
     for c in range(3):
-        u[c] = np.fft.irfftn(uh[c], s=(n, n, n), axes=(0, 1, 2))
-    u -= u.reshape(3, -1).mean(axis=1)[:, None, None, None]
-    rms = np.sqrt((u.astype(np.float64) ** 2).mean() )
+        u[c] = sfft.irfftn(xi[c], s=(n, n, n), axes=(0, 1, 2), workers=workers)
+    del xi
+    for c in range(3):
+        u[c] -= u[c].mean()
+    rms = np.sqrt(sum(float(np.mean(np.square(u[c], dtype=np.float64))) for c in range(3)) / 3.0)
     u *= u_rms / rms
     return np.ones((n, n, n), dtype=dtype), u
 
