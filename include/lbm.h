@@ -141,6 +141,18 @@ int lbm_global_moments(lbm_ctx *ctx, double *mass, double mom[3], double *kin_en
  * FP64 f[27][n]. Synchronises. */
 int lbm_get_pops(lbm_ctx *ctx, double *f);
 
+/* Populations f_i (not shifted) of m chosen cells (linear indices
+ * cells[k] < n, host array) into host f[m][27]. For spot checks of large
+ * lattices. Synchronises. */
+int lbm_sample_pops(lbm_ctx *ctx, const size_t *cells, size_t m, double *f);
+
+/* Box-filtered fields on the coarse grid of w^3-cell blocks (nx, ny, nz
+ * divisible by w): out[10][nc], nc = n / w^3, holding the block means of
+ * rho, ux, uy, uz, ux ux, uy uy, uz uz, ux uy, ux uz, uy uz (u as in
+ * lbm_get_fields). Used to build training data for the learned closure.
+ * Synchronises. */
+int lbm_get_filtered(lbm_ctx *ctx, int w, double *out);
+
 /* Number of completed steps. */
 int lbm_time(const lbm_ctx *ctx, long *t);
 
@@ -152,6 +164,31 @@ int lbm_set_force_field(lbm_ctx *ctx, const double *F);
  * b2[32] w3[32] b3 mu[6] sigma[6] nu_scale); the matrix weights are used in
  * bfloat16 on the matrix cores, the rest in float32. */
 int lbm_set_closure_weights(lbm_ctx *ctx, const float *w, size_t n);
+
+/* ---- learned closure training (device-resident batches) ----
+ * A trainer holds FP32 master parameters, Adam moments and the bfloat16
+ * matrix-core copy of the closure network (same 1326-float layout as
+ * lbm_set_closure_weights). Feature batches are device arrays d_feat[m][6]
+ * (the six closure inputs per cell) with scaled targets d_target[m] =
+ * nu_t / nu_scale; the loss is mean((softplus(z) - target)^2). */
+typedef struct lbm_mlp lbm_mlp;
+int lbm_mlp_create(void *stream, lbm_mlp **out);
+int lbm_mlp_destroy(lbm_mlp *m);
+/* Set all parameters (host blob) and reset the Adam state. */
+int lbm_mlp_set_params(lbm_mlp *m, const float *blob, size_t n);
+/* Current parameters into a host blob of 1326 floats. Synchronises. */
+int lbm_mlp_get_params(lbm_mlp *m, float *blob, size_t n);
+/* Eddy viscosity nu_t for m cells: device d_feat[m][6] -> device d_nu[m]. */
+int lbm_mlp_forward(lbm_mlp *m, const float *d_feat, size_t count, float *d_nu);
+/* Loss and gradient of one batch (kept on the device for lbm_mlp_adam_step;
+ * copied to host grad[1313] when grad is not NULL, which synchronises). The
+ * batch loss is added to an accumulator read by lbm_mlp_take_loss. */
+int lbm_mlp_loss_grad(lbm_mlp *m, const float *d_feat, const float *d_target, size_t count, float *grad);
+/* One Adam update (Kingma and Ba 2015) with the last gradient. */
+int lbm_mlp_adam_step(lbm_mlp *m, float lr, float beta1, float beta2, float eps);
+/* Mean loss over the batches since the last call; resets. Synchronises. */
+int lbm_mlp_take_loss(lbm_mlp *m, double *mean_loss);
+const char *lbm_mlp_last_error(const lbm_mlp *m);
 
 /* Checkpoint: raw population store, outflow ghost plane, time and layout
  * parity. lbm_state_bytes gives the size. Synchronises. */

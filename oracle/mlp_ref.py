@@ -98,7 +98,10 @@ def loss_and_grad(blob, feats, target_scaled, emulate_bf16=False):
     da2 = np.outer(dz, c["w3"]) * (c["a2"] > 0)          # (B, 32)
     g[SL["W2"][0]] = (da2.T @ c["h1"]).reshape(-1)
     g[SL["b2"][0]] = da2.sum(axis=0)
-    da1 = (da2 @ c["W2"]) * (c["a1"] > 0)                # (B, 32)
+    # with the bf16 emulation the backward data product takes da2 in bfloat16
+    # (as the matrix cores do); the weight sums keep it in full precision
+    da2_mm = bf16(da2) if emulate_bf16 else da2
+    da1 = (da2_mm @ c["W2"]) * (c["a1"] > 0)             # (B, 32)
     g[SL["W1"][0]] = (da1.T @ c["xh"]).reshape(-1)
     g[SL["b1"][0]] = da1.sum(axis=0)
     return L, g

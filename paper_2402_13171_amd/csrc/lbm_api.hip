@@ -477,6 +477,28 @@ int lbm_get_fields(lbm_ctx *c, double *rho, double *u) {
     return LBM_OK;
 }
 
+int lbm_get_filtered(lbm_ctx *c, int w, double *out) {
+    int rc = ready(c);
+    if (rc) return rc;
+    if (!out || w < 1 || c->cfg.nx % w || c->cfg.ny % w || c->cfg.nz % w)
+        return fail(c, LBM_EINVAL, "filter width must divide nx, ny and nz");
+    const size_t nc = c->n / ((size_t)w * w * w);
+    const size_t ch = nc < ((size_t)1 << 20) ? nc : ((size_t)1 << 20);
+    if ((rc = ensure_stage(c, 10 * ch * sizeof(double)))) return rc;
+    Geo g = geo_of(c);
+    Physics ph = physics_of(c);
+    for (size_t c0 = 0; c0 < nc; c0 += ch) {
+        const size_t m = nc - c0 < ch ? nc - c0 : ch;
+        if (launch_filtered((int)c->cfg.storage, c->parity, g, ph, w, c->d_stage, c0, m, c->stream))
+            return fail(c, LBM_EHIP, "filter launch");
+        for (int k = 0; k < 10; ++k)
+            HIPCHK(c, hipMemcpyAsync(out + (size_t)k * nc + c0, c->d_stage + (size_t)k * m, m * sizeof(double),
+                                     hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    return LBM_OK;
+}
+
 int lbm_get_pops(lbm_ctx *c, double *f) {
     int rc = ready(c);
     if (rc) return rc;
@@ -493,6 +515,25 @@ int lbm_get_pops(lbm_ctx *c, double *f) {
                                      hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
     }
+    return LBM_OK;
+}
+
+int lbm_sample_pops(lbm_ctx *c, const size_t *cells, size_t m, double *f) {
+    int rc = ready(c);
+    if (rc) return rc;
+    if (!cells || !f) return fail(c, LBM_EINVAL, "null argument");
+    if (m == 0) return LBM_OK;
+    for (size_t k = 0; k < m; ++k)
+        if (cells[k] >= c->n) return fail(c, LBM_EINVAL, "cell index %zu out of range", cells[k]);
+    const size_t bytes = m * sizeof(size_t) + 27 * m * sizeof(double);
+    if ((rc = ensure_stage(c, round_up(bytes, 256)))) return rc;
+    double *d_f = c->d_stage;
+    size_t *d_cells = (size_t *)(c->d_stage + 27 * m);
+    HIPCHK(c, hipMemcpyAsync(d_cells, cells, m * sizeof(size_t), hipMemcpyHostToDevice, c->stream));
+    if (launch_sample_pops((int)c->cfg.storage, c->parity, geo_of(c), d_cells, m, d_f, c->stream))
+        return fail(c, LBM_EHIP, "sample launch");
+    HIPCHK(c, hipMemcpyAsync(f, d_f, 27 * m * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
     return LBM_OK;
 }
 
@@ -551,7 +592,18 @@ int lbm_set_force_field(lbm_ctx *c, const double *F) {
 int lbm_set_closure_weights(lbm_ctx *c, const float *w, size_t n) {
     if (!c) return LBM_EINVAL;
     if (!w || n != (size_t)MLP_NBLOB) return fail(c, LBM_EINVAL, "expected %d closure parameters", MLP_NBLOB);
-    return fail(c, LBM_EINVAL, "learned closure not available in this build");
+    for (int j = 0; j < 6; ++j)
+        if (!(w[MLP_NPARAM + 6 + j] > 0.0f)) return fail(c, LBM_EINVAL, "sigma must be positive");
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    if (!c->d_mlp && hipMalloc((void **)&c->d_mlp, sizeof(MlpDev)) != hipSuccess) {
+        c->d_mlp = nullptr;
+        return fail(c, LBM_ENOMEM, "closure weights");
+    }
+    MlpDev h;
+    mlp_pack(w, &h);
+    HIPCHK(c, hipMemcpy(c->d_mlp, &h, sizeof h, hipMemcpyHostToDevice));
+    c->mlp_set = true;
+    return LBM_OK;
 }
 
 int lbm_state_bytes(const lbm_ctx *c, size_t *bytes) {

@@ -23,10 +23,14 @@ struct ForceBox {
 struct MlpDev {
     uint16_t W1[32 * 8];    // [out][in], inputs padded 6 -> 8 with zeros
     uint16_t W2[32 * 32];   // [out][in]
+    uint16_t W2T[32 * 32];  // [in][out] (backward pass)
     float b1[32], b2[32], w3[32], b3;
     float mu[8], inv_sigma[8];
     float nu_scale;
 };
+constexpr int MLP_NPARAM = 1313;
+// host: closure parameter blob (1326 floats) -> device layout
+void mlp_pack(const float *blob, MlpDev *out);
 
 // Everything a lattice kernel needs, passed by value.
 struct Geo {
@@ -77,6 +81,10 @@ int launch_fields(int storage, int parity, const Geo &g, const Physics &ph, doub
                   size_t cell0, size_t ncell, hipStream_t s);
 int launch_pops(int storage, int parity, const Geo &g, double *f, size_t cell0, size_t ncell,
                 hipStream_t s);
+int launch_sample_pops(int storage, int parity, const Geo &g, const size_t *cells, size_t m, double *f,
+                       hipStream_t s);
+int launch_filtered(int storage, int parity, const Geo &g, const Physics &ph, int w, double *out, size_t cc0,
+                    size_t ncc, hipStream_t s);
 int launch_moments(int storage, int parity, const Geo &g, const Physics &ph, double *partials,
                    int nblocks, double *out, hipStream_t s);
 int launch_check(int storage, int parity, const Geo &g, const Physics &ph, double *partials,

@@ -27,6 +27,7 @@
 // Each rule mirrors the two-array pull with the same boundary readings, and
 // every slot keeps exactly one reader and one writer per step.
 #include "lbm_access.h"
+#include "lbm_mlp_dev.h"
 
 namespace lbm {
 
@@ -81,12 +82,18 @@ __global__ __launch_bounds__(256) void k_stream_collide(Geo g, Physics ph) {
     const int x = blockIdx.x * 64 + threadIdx.x;
     const int y = blockIdx.y * 4 + threadIdx.y;
     const int z = blockIdx.z;
-    if (x >= g.nx || y >= g.ny) return;
+    // the learned closure runs on the matrix cores, which need every lane of
+    // the wave: out-of-range lanes then compute on a rest state and store nothing
+    const bool valid = x < g.nx && y < g.ny;
+    if (CL != CL_MLP && !valid) return;
     const size_t cell = cidx(g, x, y, z);
     float d[27];
     int xs[3];
     size_t rows[9];
-    if (PAR == 0) {
+    if (CL == CL_MLP && !valid) {
+#pragma unroll
+        for (int i = 0; i < 27; ++i) d[i] = 0.0f;
+    } else if (PAR == 0) {
         Unroll<T, 0>::read_natural(g, cell, d);
     } else if (!BCG) {
         xs[0] = x == 0 ? g.nx - 1 : x - 1;
@@ -104,11 +111,20 @@ __global__ __launch_bounds__(256) void k_stream_collide(Geo g, Physics ph) {
     }
 
     float Fx = 0.f, Fy = 0.f, Fz = 0.f;
-    if (FRC) cell_force(ph, (size_t)g.nx * g.ny * g.nz, cell, x, y, z, Fx, Fy, Fz);
+    if (FRC && valid) cell_force(ph, (size_t)g.nx * g.ny * g.nz, cell, x, y, z, Fx, Fy, Fz);
     const CellMoments m = moments_of(d, Fx, Fy, Fz);
-    const float om1 = omega1_of<CL>(m, ph);
+    float om1;
+    if (CL == CL_MLP) {
+        float f[6];
+        closure_features(m, ph.tau0, f);
+        const float nut = mlp_nu_t_wave(*ph.mlp, f);
+        om1 = 1.0f / (3.0f * (ph.nu0 + nut) + 0.5f);
+    } else {
+        om1 = omega1_of<CL>(m, ph);
+    }
     float o[27];
     collide_unit_rates(m, om1, ph.omega2, Fx, Fy, Fz, o);
+    if (CL == CL_MLP && !valid) return;
 
     if (PAR == 0) {
         Unroll<T, 0>::write_swap_local(g, cell, o);
@@ -144,6 +160,7 @@ static int launch_sc_cl(int closure, bool bcg, bool frc, const Geo &g, const Phy
     switch (closure) {
         case CL_NONE: launch_sc<T, PAR, CL_NONE>(bcg, frc, g, ph, s); return 0;
         case CL_SMAG: launch_sc<T, PAR, CL_SMAG>(bcg, frc, g, ph, s); return 0;
+        case CL_MLP: launch_sc<T, PAR, CL_MLP>(bcg, frc, g, ph, s); return 0;
         default: return -1;
     }
 }
@@ -255,6 +272,89 @@ __global__ void k_pops(Geo g, double *f, size_t cell0, size_t ncell) {
             f[(size_t)i * ncell + q] = w + (double)d[i];
         }
     }
+}
+
+template <typename T, int PAR>
+__global__ void k_sample_pops(Geo g, const size_t *cells, size_t m, double *f) {
+    const size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (q >= m) return;
+    const size_t c = cells[q];
+    const int x = (int)(c % g.nx), y = (int)((c / g.nx) % g.ny), z = (int)(c / ((size_t)g.nx * g.ny));
+    float d[27];
+    read_cell<T, PAR>(g, c, x, y, z, d);
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+        const double w = (cx_of(i) == 0 ? 2.0 / 3.0 : 1.0 / 6.0) * (cy_of(i) == 0 ? 2.0 / 3.0 : 1.0 / 6.0) *
+                         (cz_of(i) == 0 ? 2.0 / 3.0 : 1.0 / 6.0);
+        f[q * 27 + i] = w + (double)d[i];
+    }
+}
+
+template <typename T, int PAR>
+static void sample_t(const Geo &g, const size_t *cells, size_t m, double *f, hipStream_t s) {
+    k_sample_pops<T, PAR><<<(unsigned)((m + 255) / 256), 256, 0, s>>>(g, cells, m, f);
+}
+int launch_sample_pops(int storage, int parity, const Geo &g, const size_t *cells, size_t m, double *f,
+                       hipStream_t s) {
+    switch (storage * 2 + parity) {
+        case 0: sample_t<float, 0>(g, cells, m, f, s); break;
+        case 1: sample_t<float, 1>(g, cells, m, f, s); break;
+        case 2: sample_t<__half, 0>(g, cells, m, f, s); break;
+        case 3: sample_t<__half, 1>(g, cells, m, f, s); break;
+        case 4: sample_t<bf16_t, 0>(g, cells, m, f, s); break;
+        case 5: sample_t<bf16_t, 1>(g, cells, m, f, s); break;
+        default: return -1;
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+// block means over w^3 cells: rho, u, u u (coarse cells cc0 .. cc0+ncc)
+template <typename T, int PAR>
+__global__ void k_filtered(Geo g, Physics ph, int w, double *out, size_t cc0, size_t ncc) {
+    const size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (q >= ncc) return;
+    const int cnx = g.nx / w, cny = g.ny / w;
+    const size_t cc = cc0 + q;
+    const int X = (int)(cc % cnx), Y = (int)((cc / cnx) % cny), Z = (int)(cc / ((size_t)cnx * cny));
+    double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int dz = 0; dz < w; ++dz)
+        for (int dy = 0; dy < w; ++dy)
+            for (int dx = 0; dx < w; ++dx) {
+                const int x = X * w + dx, y = Y * w + dy, z = Z * w + dz;
+                double r, ux, uy, uz;
+                cell_macro<T, PAR>(g, ph, cidx(g, x, y, z), x, y, z, r, ux, uy, uz);
+                acc[0] += r;
+                acc[1] += ux;
+                acc[2] += uy;
+                acc[3] += uz;
+                acc[4] += ux * ux;
+                acc[5] += uy * uy;
+                acc[6] += uz * uz;
+                acc[7] += ux * uy;
+                acc[8] += ux * uz;
+                acc[9] += uy * uz;
+            }
+    const double inv = 1.0 / ((double)w * w * w);
+#pragma unroll
+    for (int k = 0; k < 10; ++k) out[(size_t)k * ncc + q] = acc[k] * inv;
+}
+
+template <typename T, int PAR>
+static void filtered_t(const Geo &g, const Physics &ph, int w, double *out, size_t cc0, size_t ncc, hipStream_t s) {
+    k_filtered<T, PAR><<<(unsigned)((ncc + 127) / 128), 128, 0, s>>>(g, ph, w, out, cc0, ncc);
+}
+int launch_filtered(int storage, int parity, const Geo &g, const Physics &ph, int w, double *out, size_t cc0,
+                    size_t ncc, hipStream_t s) {
+    switch (storage * 2 + parity) {
+        case 0: filtered_t<float, 0>(g, ph, w, out, cc0, ncc, s); break;
+        case 1: filtered_t<float, 1>(g, ph, w, out, cc0, ncc, s); break;
+        case 2: filtered_t<__half, 0>(g, ph, w, out, cc0, ncc, s); break;
+        case 3: filtered_t<__half, 1>(g, ph, w, out, cc0, ncc, s); break;
+        case 4: filtered_t<bf16_t, 0>(g, ph, w, out, cc0, ncc, s); break;
+        case 5: filtered_t<bf16_t, 1>(g, ph, w, out, cc0, ncc, s); break;
+        default: return -1;
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
 template <typename T, int PAR>

@@ -23,9 +23,12 @@ MLP_NBLOB = 1326
 EXPORTS = [
     "lbm_create", "lbm_destroy", "lbm_required_bytes", "lbm_attach", "lbm_init_tgv",
     "lbm_init_fields", "lbm_set_rotor", "lbm_step", "lbm_get_fields", "lbm_rotor_loads",
-    "lbm_global_moments", "lbm_get_pops", "lbm_time", "lbm_set_force_field",
+    "lbm_global_moments", "lbm_get_pops", "lbm_sample_pops", "lbm_get_filtered", "lbm_time", "lbm_set_force_field",
     "lbm_set_closure_weights", "lbm_state_bytes", "lbm_get_state", "lbm_set_state",
     "lbm_strerror", "lbm_last_error",
+    "lbm_mlp_create", "lbm_mlp_destroy", "lbm_mlp_set_params", "lbm_mlp_get_params",
+    "lbm_mlp_forward", "lbm_mlp_loss_grad", "lbm_mlp_adam_step", "lbm_mlp_take_loss",
+    "lbm_mlp_last_error",
 ]
 
 
@@ -82,6 +85,8 @@ def lib():
         "lbm_rotor_loads": [vp, i, _D, _D],
         "lbm_global_moments": [vp, _D, _D, _D],
         "lbm_get_pops": [vp, _D],
+        "lbm_sample_pops": [vp, C.POINTER(C.c_size_t), sz, _D],
+        "lbm_get_filtered": [vp, i, _D],
         "lbm_time": [vp, C.POINTER(C.c_long)],
         "lbm_set_force_field": [vp, _D],
         "lbm_set_closure_weights": [vp, C.POINTER(C.c_float), sz],
@@ -93,6 +98,23 @@ def lib():
         fn = getattr(L, name)
         fn.argtypes = args
         fn.restype = C.c_int
+    fp = C.POINTER(C.c_float)
+    msig = {
+        "lbm_mlp_create": [vp, C.POINTER(vp)],
+        "lbm_mlp_destroy": [vp],
+        "lbm_mlp_set_params": [vp, fp, sz],
+        "lbm_mlp_get_params": [vp, fp, sz],
+        "lbm_mlp_forward": [vp, vp, sz, vp],
+        "lbm_mlp_loss_grad": [vp, vp, vp, sz, fp],
+        "lbm_mlp_adam_step": [vp, C.c_float, C.c_float, C.c_float, C.c_float],
+        "lbm_mlp_take_loss": [vp, _D],
+    }
+    for name, args in msig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = C.c_int
+    L.lbm_mlp_last_error.argtypes = [vp]
+    L.lbm_mlp_last_error.restype = C.c_char_p
     L.lbm_strerror.argtypes = [i]
     L.lbm_strerror.restype = C.c_char_p
     L.lbm_last_error.argtypes = [vp]
@@ -215,6 +237,22 @@ class Lbm:
         self._check(lib().lbm_get_pops(self._ctx, _p(f)))
         return f
 
+    def filtered(self, w):
+        """block means over w^3 cells: array [10, nz/w, ny/w, nx/w] with rho,
+        ux, uy, uz, uxux, uyuy, uzuz, uxuy, uxuz, uyuz"""
+        nz, ny, nx = self.shape
+        out = np.empty((10, nz // w, ny // w, nx // w))
+        self._check(lib().lbm_get_filtered(self._ctx, int(w), _p(out)))
+        return out
+
+    def sample_pops(self, cells):
+        """populations f[m][27] of the given linear cell indices"""
+        cells = np.ascontiguousarray(cells, dtype=np.uint64)
+        f = np.empty((cells.size, 27))
+        self._check(lib().lbm_sample_pops(self._ctx, cells.ctypes.data_as(C.POINTER(C.c_size_t)),
+                                          cells.size, _p(f)))
+        return f
+
     def rotor_loads(self, rid, with_points=False):
         out = np.zeros(3)
         pf = np.zeros((self._npts[rid], 3))
@@ -255,3 +293,75 @@ class Lbm:
     def set_state(self, buf):
         buf = np.ascontiguousarray(buf, dtype=np.uint8)
         self._check(lib().lbm_set_state(self._ctx, C.c_void_p(buf.ctypes.data), buf.size))
+
+
+class MlpTrainer:
+    """Device-resident trainer of the closure network (lbm_mlp_* entry
+    points). Batches are torch float32 CUDA tensors: features [m, 6] and
+    scaled targets [m]."""
+
+    def __init__(self, blob, device="cuda:0"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.stream = torch.cuda.Stream(device=self.device)
+        self._h = C.c_void_p()
+        rc = lib().lbm_mlp_create(C.c_void_p(self.stream.cuda_stream), C.byref(self._h))
+        if rc != OK:
+            raise LbmError(rc, lib().lbm_strerror(rc).decode())
+        self.set_params(blob)
+
+    def _check(self, rc):
+        if rc != OK:
+            raise LbmError(rc, lib().lbm_strerror(rc).decode() + " (" +
+                           lib().lbm_mlp_last_error(self._h).decode() + ")")
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().lbm_mlp_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, blob):
+        w = np.ascontiguousarray(blob, dtype=np.float32)
+        self._check(lib().lbm_mlp_set_params(self._h, w.ctypes.data_as(C.POINTER(C.c_float)), w.size))
+
+    def get_params(self):
+        w = np.empty(MLP_NBLOB, dtype=np.float32)
+        self._check(lib().lbm_mlp_get_params(self._h, w.ctypes.data_as(C.POINTER(C.c_float)), w.size))
+        return w
+
+    def _sync_inputs(self, *tensors):
+        # the inputs were produced on torch's current stream
+        self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
+        for t in tensors:
+            assert t.is_cuda and t.dtype == self.torch.float32 and t.is_contiguous()
+
+    def forward(self, feat):
+        self._sync_inputs(feat)
+        out = self.torch.empty(feat.shape[0], dtype=self.torch.float32, device=self.device)
+        self._check(lib().lbm_mlp_forward(self._h, C.c_void_p(feat.data_ptr()), feat.shape[0],
+                                          C.c_void_p(out.data_ptr())))
+        self.torch.cuda.current_stream(self.device).wait_stream(self.stream)
+        return out
+
+    def loss_grad(self, feat, target, want_grad=False):
+        self._sync_inputs(feat, target)
+        g = np.empty(1313, dtype=np.float32) if want_grad else None
+        gp = g.ctypes.data_as(C.POINTER(C.c_float)) if want_grad else None
+        self._check(lib().lbm_mlp_loss_grad(self._h, C.c_void_p(feat.data_ptr()),
+                                            C.c_void_p(target.data_ptr()), feat.shape[0], gp))
+        return g
+
+    def adam_step(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        self._check(lib().lbm_mlp_adam_step(self._h, lr, beta1, beta2, eps))
+
+    def take_loss(self):
+        v = C.c_double()
+        self._check(lib().lbm_mlp_take_loss(self._h, C.byref(v)))
+        return v.value

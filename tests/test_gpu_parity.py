@@ -179,3 +179,21 @@ def test_stable_run_passes_checks():
     sim.init_tgv(0.05)
     sim.step(20)
     assert sim.time == 20
+
+
+def test_box_filter_matches_block_means_of_oracle_fields():
+    _need_gpu()
+    n, w = 16, 4
+    sim, ref = make_pair(n, n, n, omega=1.7)
+    rho, u = random_field(n, n, n, seed=31)
+    sim.init_fields(rho, u)
+    ref.init_fields(rho, u)
+    sim.step(3)
+    ref.step(3)
+    got = sim.filtered(w)
+    r, uu = ref.fields()
+    blk = lambda a: a.reshape(n // w, w, n // w, w, n // w, w).mean(axis=(1, 3, 5))
+    expect = [blk(r), blk(uu[0]), blk(uu[1]), blk(uu[2]), blk(uu[0] * uu[0]), blk(uu[1] * uu[1]),
+              blk(uu[2] * uu[2]), blk(uu[0] * uu[1]), blk(uu[0] * uu[2]), blk(uu[1] * uu[2])]
+    for k in range(10):
+        assert np.abs(got[k] - expect[k]).max() <= 1e-7, k
