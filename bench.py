@@ -51,6 +51,31 @@ def time_variant(n, rho, u, storage, closure, steps, warmup, blob=None):
     return {"mlups": mlups, "ms_per_step": ms / steps, "wall_s": wall, "mass": m, "ke": ke}
 
 
+def copy_bandwidth(gib=4, reps=10):
+    """Achievable HBM bandwidth: the library's streaming copy kernel over two
+    gib-GiB buffers (bytes read + bytes written per second), as the paper
+    takes b_S from the STREAM copy kernel."""
+    import torch
+    from paper_2402_13171_amd.lbm import copy_probe
+    nb = gib << 30
+    a = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    copy_probe(a, b, s)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        copy_probe(a, b, s)
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    ok = bool(torch.equal(a[:1024], b[:1024]))
+    del a, b
+    torch.cuda.empty_cache()
+    return {"GBps": 2 * nb / (ms * 1e-3) / 1e9, "ms_per_copy": ms, "bytes": nb, "verified": ok}
+
+
 def cpu_baseline(sample_n=128, steps=100):
     """The FP64 oracle on the host cores, on a bounded sample of the same
     recipe (a sample_n^3 periodic box, same spectrum and omega)."""
@@ -91,6 +116,10 @@ def main():
     t0 = time.perf_counter()
     rho, u = workloads.random_phase_field(n, seed=0)
     log(f"bench: field ready in {time.perf_counter() - t0:.1f} s")
+
+    log("bench: copy-kernel bandwidth probe (2 x 4 GiB)")
+    cbw = copy_bandwidth()
+    log(f"bench: copy probe {cbw['GBps']:.0f} GB/s")
 
     results = {}
     for v in args.variants.split(","):
@@ -137,6 +166,9 @@ def main():
                      "kernel": "k_stream_collide", "bytes_per_lup": nb,
                      "bytes_per_launch": nb * n ** 3},
         "cpu_baseline": cpu,
+        "copy_probe": {"GBps": round(cbw["GBps"], 1), "bytes": cbw["bytes"],
+                       "frac_of_peak": round(cbw["GBps"] * 1e9 / roofline.HBM_PEAK_BPS, 4),
+                       "kernel_frac_of_copy": round(base["achieved_GBps"] / cbw["GBps"], 4)},
         "variants": {k: {"mlups": round(v["mlups"], 1), "ms_per_step": round(v["ms_per_step"], 4),
                          "achieved_GBps": round(v["achieved_GBps"], 1),
                          "hbm_frac": round(v["hbm_frac"], 4), "bytes_per_lup": v["bytes_per_lup"],

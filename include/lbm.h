@@ -119,6 +119,14 @@ typedef struct {
 } lbm_rotor;
 int lbm_set_rotor(lbm_ctx *ctx, int rotor_id, const lbm_rotor *rotor);
 
+/* Time-dependent inlet for bc_x inflow/outflow: the inlet velocity of cell
+ * (y,z) at step t is mean[q] + turbulence taken from a frozen periodic box
+ * convected through the inlet (Taylor's hypothesis): with s = advect * t
+ * (mod lt), the box slice at s, linearly interpolated between slices
+ * floor(s) and floor(s)+1. q = y + ny*z. Host FP64 arrays mean[3][ny*nz]
+ * and box[3][lt][ny*nz] (box may be NULL: steady mean inlet). Copied. */
+int lbm_set_inflow(lbm_ctx *ctx, const double *mean, const double *box, int lt, double advect);
+
 /* Enqueue n time steps. With check_every > 0, an FP64 mass and NaN check
  * runs every check_every steps and at the end; the call then synchronises
  * and returns LBM_EUNSTABLE if a check failed. */
@@ -195,6 +203,13 @@ const char *lbm_mlp_last_error(const lbm_mlp *m);
 int lbm_state_bytes(const lbm_ctx *ctx, size_t *bytes);
 int lbm_get_state(lbm_ctx *ctx, void *host_buf, size_t bytes);
 int lbm_set_state(lbm_ctx *ctx, const void *host_buf, size_t bytes);
+
+/* Device-to-device copy of `bytes` (multiple of 16, 16-byte aligned device
+ * pointers) with a plain streaming kernel, enqueued on `stream` (hipStream_t
+ * or NULL). It measures achievable HBM bandwidth, the reference the paper
+ * takes from the STREAM copy kernel (Sec. 4.3), and calibrates hardware
+ * traffic counters against a kernel of known traffic. */
+int lbm_copy_probe(const void *d_src, void *d_dst, size_t bytes, void *stream);
 
 const char *lbm_strerror(int code);
 const char *lbm_last_error(const lbm_ctx *ctx);

@@ -207,6 +207,24 @@ def blade_element(rho, wn, wt, chord, dl, twist_deg, pitch_deg, polar):
     return fn.value, ft.value, al.value
 
 
+def inflow_plane(mean, box, advect, t):
+    """Inlet velocity at step t for the turbine-row case (reading: a frozen
+    periodic turbulence box convected through the inlet, Taylor's
+    hypothesis): mean[3, nz, ny] plus the box[3, lt, nz, ny] slice at
+    s = advect * t (mod lt), linearly interpolated between slices."""
+    mean = np.asarray(mean, dtype=np.float64)
+    if box is None:
+        return mean.copy()
+    lt = box.shape[1]
+    s = np.fmod(advect * t, lt)
+    if s < 0:
+        s += lt
+    s0 = min(int(np.floor(s)), lt - 1)
+    s1 = (s0 + 1) % lt
+    f = s - s0
+    return mean + (1.0 - f) * box[:, s0] + f * box[:, s1]
+
+
 # ---------------------------------------------------------------- domain solver
 class Grid:
     """Two-array FP64 solver on an nx x ny x nz box (x fastest)."""

@@ -147,6 +147,48 @@ struct Unroll {
         Unroll<T, I + 1>::write_periodic(g, xs, rows, o);
     }
 };
+// Fast-path variants with 32-bit byte offsets from per-plane base pointers:
+// the plane base is uniform across the wave (scalar registers), so each access
+// is one global load/store with a 32-bit vector offset. Valid while
+// n * sizeof(T) < 2^32 (checked on the host, which otherwise uses the
+// 64-bit general path).
+template <typename T, int I>
+struct Unroll32 {
+    static __device__ __forceinline__ const char *plane(const Geo &g, int i) {
+        return (const char *)g.pops + (size_t)i * g.P * sizeof(T);
+    }
+    static __device__ __forceinline__ void read_natural(const Geo &g, uint32_t boff, float *d) {
+        d[I] = Store<T>::ld((const T *)(plane(g, I) + boff));
+        Unroll32<T, I + 1>::read_natural(g, boff, d);
+    }
+    static __device__ __forceinline__ void write_swap_local(const Geo &g, uint32_t boff, const float *o) {
+        Store<T>::st((T *)(plane(g, 26 - I) + boff), o[I]);
+        Unroll32<T, I + 1>::write_swap_local(g, boff, o);
+    }
+    // rows[(dy+1) + 3 (dz+1)] and xs[dx+1] are element offsets of the wrapped neighbours
+    static __device__ __forceinline__ void read_periodic(const Geo &g, const uint32_t *xs, const uint32_t *rows,
+                                                         float *d) {
+        constexpr int cx = cx_of(I), cy = cy_of(I), cz = cz_of(I);
+        const uint32_t boff = (rows[(1 - cy) + 3 * (1 - cz)] + xs[1 - cx]) * (uint32_t)sizeof(T);
+        d[I] = Store<T>::ld((const T *)(plane(g, 26 - I) + boff));
+        Unroll32<T, I + 1>::read_periodic(g, xs, rows, d);
+    }
+    static __device__ __forceinline__ void write_periodic(const Geo &g, const uint32_t *xs, const uint32_t *rows,
+                                                          const float *o) {
+        constexpr int cx = cx_of(I), cy = cy_of(I), cz = cz_of(I);
+        const uint32_t boff = (rows[(1 + cy) + 3 * (1 + cz)] + xs[1 + cx]) * (uint32_t)sizeof(T);
+        Store<T>::st((T *)(plane(g, I) + boff), o[I]);
+        Unroll32<T, I + 1>::write_periodic(g, xs, rows, o);
+    }
+};
+template <typename T>
+struct Unroll32<T, 27> {
+    static __device__ __forceinline__ void read_natural(const Geo &, uint32_t, float *) {}
+    static __device__ __forceinline__ void write_swap_local(const Geo &, uint32_t, const float *) {}
+    static __device__ __forceinline__ void read_periodic(const Geo &, const uint32_t *, const uint32_t *, float *) {}
+    static __device__ __forceinline__ void write_periodic(const Geo &, const uint32_t *, const uint32_t *, const float *) {}
+};
+
 template <typename T>
 struct Unroll<T, 27> {
     static __device__ __forceinline__ void read_natural(const Geo &, size_t, float *) {}

@@ -51,6 +51,9 @@ struct lbm_ctx {
     bool mass0_set = false;
     double *d_stage = nullptr;
     size_t stage_bytes = 0;
+    float *d_in_mean = nullptr, *d_in_box = nullptr;  // time-dependent inlet
+    int in_lt = 0;
+    double in_advect = 0.0;
     std::string err;
 };
 
@@ -109,8 +112,11 @@ Physics physics_of(const lbm_ctx *c) {
     return ph;
 }
 
+// The fast stream-collide path needs an all-periodic box and 32-bit byte
+// offsets within one population plane; everything else takes the general path.
 bool general_bc(const lbm_ctx *c) {
-    return c->cfg.bc_x != LBM_BC_PERIODIC || c->cfg.bc_z_lo != LBM_BC_PERIODIC || c->cfg.bc_z_hi != LBM_BC_PERIODIC;
+    return c->cfg.bc_x != LBM_BC_PERIODIC || c->cfg.bc_z_lo != LBM_BC_PERIODIC || c->cfg.bc_z_hi != LBM_BC_PERIODIC ||
+           c->P * c->esize >= ((size_t)1 << 32);
 }
 
 int ensure_stage(lbm_ctx *c, size_t bytes) {
@@ -265,6 +271,8 @@ int lbm_destroy(lbm_ctx *c) {
     if (c->d_ffield) (void)hipFree(c->d_ffield);
     if (c->d_mlp) (void)hipFree(c->d_mlp);
     if (c->d_stage) (void)hipFree(c->d_stage);
+    if (c->d_in_mean) (void)hipFree(c->d_in_mean);
+    if (c->d_in_box) (void)hipFree(c->d_in_box);
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
     delete c;
     return LBM_OK;
@@ -414,6 +422,44 @@ int lbm_set_rotor(lbm_ctx *c, int id, const lbm_rotor *r) {
     return refresh_rotor_table(c);
 }
 
+int lbm_set_inflow(lbm_ctx *c, const double *mean, const double *box, int lt, double advect) {
+    int rc = ready(c);
+    if (rc) return rc;
+    if (c->cfg.bc_x != LBM_BC_INFLOW_OUTFLOW) return fail(c, LBM_EINVAL, "the x boundary is not inflow/outflow");
+    if (!mean || (box && lt < 1) || !std::isfinite(advect)) return fail(c, LBM_EINVAL, "bad inflow arguments");
+    (void)hipStreamSynchronize(c->stream);
+    const size_t plane = (size_t)c->cfg.ny * c->cfg.nz;
+    if (c->d_in_mean) (void)hipFree(c->d_in_mean);
+    if (c->d_in_box) (void)hipFree(c->d_in_box);
+    c->d_in_mean = c->d_in_box = nullptr;
+    c->in_lt = 0;
+    std::vector<float> tmp(3 * plane);
+    for (size_t k = 0; k < 3 * plane; ++k) tmp[k] = (float)mean[k];
+    if (hipMalloc((void **)&c->d_in_mean, 3 * plane * sizeof(float)) != hipSuccess) {
+        c->d_in_mean = nullptr;
+        return fail(c, LBM_ENOMEM, "inflow mean plane");
+    }
+    HIPCHK(c, hipMemcpy(c->d_in_mean, tmp.data(), tmp.size() * sizeof(float), hipMemcpyHostToDevice));
+    if (box) {
+        const size_t nb = 3 * (size_t)lt * plane;
+        std::vector<float> tb(nb);
+        for (size_t k = 0; k < nb; ++k) tb[k] = (float)box[k];
+        if (hipMalloc((void **)&c->d_in_box, nb * sizeof(float)) != hipSuccess) {
+            c->d_in_box = nullptr;
+            return fail(c, LBM_ENOMEM, "inflow turbulence box");
+        }
+        HIPCHK(c, hipMemcpy(c->d_in_box, tb.data(), nb * sizeof(float), hipMemcpyHostToDevice));
+        c->in_lt = lt;
+    }
+    c->in_advect = advect;
+    // plane of the current time step
+    if (launch_inflow((float *)((char *)c->aux + c->off_uin), c->d_in_mean, c->d_in_box, c->in_lt > 0 ? c->in_lt : 1,
+                      (int)plane, c->in_advect * (double)c->t, c->stream))
+        return fail(c, LBM_EHIP, "inflow launch");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
 int lbm_step(lbm_ctx *c, int nsteps) {
     int rc = ready(c);
     if (rc) return rc;
@@ -436,6 +482,10 @@ int lbm_step(lbm_ctx *c, int nsteps) {
     for (int s = 0; s < nsteps; ++s) {
         Physics ph = physics_of(c);
         const bool frc = has_force(c);
+        if (c->d_in_mean &&
+            launch_inflow((float *)((char *)c->aux + c->off_uin), c->d_in_mean, c->d_in_box, c->in_lt > 0 ? c->in_lt : 1,
+                          c->cfg.ny * c->cfg.nz, c->in_advect * (double)c->t, c->stream))
+            return fail(c, LBM_EHIP, "inflow launch failed");
         if (nrot > 0 && launch_alm(st, c->parity, g, ph, c->h_rots.data(), c->d_rots, nrot, c->t, c->stream))
             return fail(c, LBM_EHIP, "actuator-line launch failed");
         if (launch_stream_collide(st, c->parity, (int)c->cfg.closure, bcg, frc, g, ph, c->stream))

@@ -85,6 +85,8 @@ int launch_sample_pops(int storage, int parity, const Geo &g, const size_t *cell
                        hipStream_t s);
 int launch_filtered(int storage, int parity, const Geo &g, const Physics &ph, int w, double *out, size_t cc0,
                     size_t ncc, hipStream_t s);
+int launch_inflow(float *uin, const float *mean, const float *box, int lt, int plane, double s_pos,
+                  hipStream_t s);
 int launch_moments(int storage, int parity, const Geo &g, const Physics &ph, double *partials,
                    int nblocks, double *out, hipStream_t s);
 int launch_check(int storage, int parity, const Geo &g, const Physics &ph, double *partials,

@@ -77,35 +77,51 @@ __device__ __forceinline__ void odd_boundary_extras(const Geo &g, int x, int y, 
     }
 }
 
+// Workgroups are dealt round-robin to the 8 XCDs (each with its own L2).
+// Renumber them so that XCD j works through one contiguous range of tiles:
+// tiles adjacent in x (whose odd-step reads share cache lines at the tile
+// edge) and in y then land on the same L2. Bijective for any tile count.
+__device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned total) {
+    constexpr unsigned NX = 8;
+    const unsigned q = total / NX, r = total % NX;
+    const unsigned xcd = b % NX, local = b / NX;
+    return xcd < r ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
+}
+
+// One workgroup = one tile of 64 (x) by 4 (y) cells in one z plane; a wave
+// is one 64-cell row segment.
 template <typename T, int PAR, int CL, bool BCG, bool FRC>
-__global__ __launch_bounds__(256) void k_stream_collide(Geo g, Physics ph) {
-    const int x = blockIdx.x * 64 + threadIdx.x;
-    const int y = blockIdx.y * 4 + threadIdx.y;
-    const int z = blockIdx.z;
+__global__ __launch_bounds__(256) void k_stream_collide(Geo g, Physics ph, unsigned gx, unsigned gy, unsigned total) {
+    const unsigned tile = xcd_tile(blockIdx.x, total);
+    const int x = (int)(tile % gx) * 64 + threadIdx.x;
+    const int y = (int)((tile / gx) % gy) * 4 + threadIdx.y;
+    const int z = (int)(tile / (gx * gy));
     // the learned closure runs on the matrix cores, which need every lane of
     // the wave: out-of-range lanes then compute on a rest state and store nothing
     const bool valid = x < g.nx && y < g.ny;
     if (CL != CL_MLP && !valid) return;
     const size_t cell = cidx(g, x, y, z);
+    // fast path (no boundary rules): 32-bit offsets, see Unroll32
+    const uint32_t cell32 = (uint32_t)cell;
     float d[27];
-    int xs[3];
-    size_t rows[9];
+    uint32_t xs[3], rows[9];
     if (CL == CL_MLP && !valid) {
 #pragma unroll
         for (int i = 0; i < 27; ++i) d[i] = 0.0f;
     } else if (PAR == 0) {
-        Unroll<T, 0>::read_natural(g, cell, d);
+        if (BCG) Unroll<T, 0>::read_natural(g, cell, d);
+        else Unroll32<T, 0>::read_natural(g, cell32 * (uint32_t)sizeof(T), d);
     } else if (!BCG) {
         xs[0] = x == 0 ? g.nx - 1 : x - 1;
         xs[1] = x;
         xs[2] = x == g.nx - 1 ? 0 : x + 1;
-        const int ys[3] = {y == 0 ? g.ny - 1 : y - 1, y, y == g.ny - 1 ? 0 : y + 1};
-        const int zs[3] = {z == 0 ? g.nz - 1 : z - 1, z, z == g.nz - 1 ? 0 : z + 1};
+        const uint32_t ys[3] = {(uint32_t)(y == 0 ? g.ny - 1 : y - 1), (uint32_t)y, (uint32_t)(y == g.ny - 1 ? 0 : y + 1)};
+        const uint32_t zs[3] = {(uint32_t)(z == 0 ? g.nz - 1 : z - 1), (uint32_t)z, (uint32_t)(z == g.nz - 1 ? 0 : z + 1)};
 #pragma unroll
         for (int b = 0; b < 3; ++b)
 #pragma unroll
-            for (int a = 0; a < 3; ++a) rows[a + 3 * b] = ((size_t)zs[b] * g.ny + ys[a]) * g.nx;
-        Unroll<T, 0>::read_periodic(g, xs, rows, d);
+            for (int a = 0; a < 3; ++a) rows[a + 3 * b] = (zs[b] * (uint32_t)g.ny + ys[a]) * (uint32_t)g.nx;
+        Unroll32<T, 0>::read_periodic(g, xs, rows, d);
     } else {
         Unroll<T, 0>::read_sw(g, x, y, z, d);
     }
@@ -127,7 +143,8 @@ __global__ __launch_bounds__(256) void k_stream_collide(Geo g, Physics ph) {
     if (CL == CL_MLP && !valid) return;
 
     if (PAR == 0) {
-        Unroll<T, 0>::write_swap_local(g, cell, o);
+        if (BCG) Unroll<T, 0>::write_swap_local(g, cell, o);
+        else Unroll32<T, 0>::write_swap_local(g, cell32 * (uint32_t)sizeof(T), o);
         if (BCG && g.bc_x == BC_INOUT && x == g.nx - 1) {
             T *G = (T *)g.ghost;
 #pragma unroll
@@ -135,7 +152,7 @@ __global__ __launch_bounds__(256) void k_stream_collide(Geo g, Physics ph) {
                 Store<T>::st(G + (size_t)(J / 3) * g.ny * g.nz + y + (size_t)g.ny * z, o[J]);
         }
     } else if (!BCG) {
-        Unroll<T, 0>::write_periodic(g, xs, rows, o);
+        Unroll32<T, 0>::write_periodic(g, xs, rows, o);
     } else {
         Unroll<T, 0>::write_push(g, x, y, z, o);
         if (g.bc_x == BC_INOUT) odd_boundary_extras<T>(g, x, y, z, o);
@@ -145,13 +162,14 @@ __global__ __launch_bounds__(256) void k_stream_collide(Geo g, Physics ph) {
 // ------------------------------------------------------------ dispatch
 template <typename T, int PAR, int CL>
 static void launch_sc(bool bcg, bool frc, const Geo &g, const Physics &ph, hipStream_t s) {
-    dim3 blk(64, 4, 1), grd((g.nx + 63) / 64, (g.ny + 3) / 4, g.nz);
+    const unsigned gx = (g.nx + 63) / 64, gy = (g.ny + 3) / 4, total = gx * gy * (unsigned)g.nz;
+    dim3 blk(64, 4, 1), grd(total, 1, 1);
     if (bcg) {
-        if (frc) k_stream_collide<T, PAR, CL, true, true><<<grd, blk, 0, s>>>(g, ph);
-        else k_stream_collide<T, PAR, CL, true, false><<<grd, blk, 0, s>>>(g, ph);
+        if (frc) k_stream_collide<T, PAR, CL, true, true><<<grd, blk, 0, s>>>(g, ph, gx, gy, total);
+        else k_stream_collide<T, PAR, CL, true, false><<<grd, blk, 0, s>>>(g, ph, gx, gy, total);
     } else {
-        if (frc) k_stream_collide<T, PAR, CL, false, true><<<grd, blk, 0, s>>>(g, ph);
-        else k_stream_collide<T, PAR, CL, false, false><<<grd, blk, 0, s>>>(g, ph);
+        if (frc) k_stream_collide<T, PAR, CL, false, true><<<grd, blk, 0, s>>>(g, ph, gx, gy, total);
+        else k_stream_collide<T, PAR, CL, false, false><<<grd, blk, 0, s>>>(g, ph, gx, gy, total);
     }
 }
 
@@ -482,4 +500,47 @@ int launch_check(int storage, int parity, const Geo &g, const Physics &ph, doubl
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
+// ------------------------------------------------------------ inlet plane
+// u_in(q) = mean(q) + (1 - f) box[s0](q) + f box[s1](q), s = s_pos mod lt
+__global__ __launch_bounds__(256) void k_inflow(float *uin, const float *mean, const float *box, int lt, int plane,
+                                                double s_pos) {
+    const int q = blockIdx.x * 256 + threadIdx.x;
+    if (q >= plane) return;
+    double sp = fmod(s_pos, (double)lt);
+    if (sp < 0.0) sp += lt;
+    int s0 = (int)floor(sp);
+    if (s0 >= lt) s0 = lt - 1;
+    const int s1 = s0 + 1 == lt ? 0 : s0 + 1;
+    const float f = (float)(sp - s0);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        float v = mean[(size_t)c * plane + q];
+        if (box) {
+            const float a = box[((size_t)c * lt + s0) * plane + q], b = box[((size_t)c * lt + s1) * plane + q];
+            v += (1.0f - f) * a + f * b;
+        }
+        uin[(size_t)c * plane + q] = v;
+    }
+}
+
+int launch_inflow(float *uin, const float *mean, const float *box, int lt, int plane, double s_pos, hipStream_t s) {
+    k_inflow<<<(plane + 255) / 256, 256, 0, s>>>(uin, mean, box, lt, plane, s_pos);
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+// ------------------------------------------------------------ copy probe
+__global__ __launch_bounds__(256) void k_copy_probe(const float4 *__restrict__ src, float4 *__restrict__ dst, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) dst[i] = src[i];
+}
+
 }  // namespace lbm
+
+extern "C" int lbm_copy_probe(const void *src, void *dst, size_t bytes, void *stream) {
+    if (!src || !dst || bytes % 16 || ((uintptr_t)src & 15) || ((uintptr_t)dst & 15)) return -1;
+    const size_t n = bytes / 16;
+    if (n == 0) return 0;
+    const size_t want = (n + 255) / 256;
+    const unsigned blocks = (unsigned)(want < 65536 ? want : 65536);
+    lbm::k_copy_probe<<<blocks, 256, 0, (hipStream_t)stream>>>((const float4 *)src, (float4 *)dst, n);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}

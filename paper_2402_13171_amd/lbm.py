@@ -22,10 +22,10 @@ MLP_NBLOB = 1326
 
 EXPORTS = [
     "lbm_create", "lbm_destroy", "lbm_required_bytes", "lbm_attach", "lbm_init_tgv",
-    "lbm_init_fields", "lbm_set_rotor", "lbm_step", "lbm_get_fields", "lbm_rotor_loads",
+    "lbm_init_fields", "lbm_set_rotor", "lbm_set_inflow", "lbm_step", "lbm_get_fields", "lbm_rotor_loads",
     "lbm_global_moments", "lbm_get_pops", "lbm_sample_pops", "lbm_get_filtered", "lbm_time", "lbm_set_force_field",
     "lbm_set_closure_weights", "lbm_state_bytes", "lbm_get_state", "lbm_set_state",
-    "lbm_strerror", "lbm_last_error",
+    "lbm_strerror", "lbm_last_error", "lbm_copy_probe",
     "lbm_mlp_create", "lbm_mlp_destroy", "lbm_mlp_set_params", "lbm_mlp_get_params",
     "lbm_mlp_forward", "lbm_mlp_loss_grad", "lbm_mlp_adam_step", "lbm_mlp_take_loss",
     "lbm_mlp_last_error",
@@ -81,6 +81,7 @@ def lib():
         "lbm_init_fields": [vp, _D, _D],
         "lbm_set_rotor": [vp, i, C.POINTER(Rotor)],
         "lbm_step": [vp, i],
+        "lbm_set_inflow": [vp, _D, _D, i, C.c_double],
         "lbm_get_fields": [vp, _D, _D],
         "lbm_rotor_loads": [vp, i, _D, _D],
         "lbm_global_moments": [vp, _D, _D, _D],
@@ -115,6 +116,8 @@ def lib():
         fn.restype = C.c_int
     L.lbm_mlp_last_error.argtypes = [vp]
     L.lbm_mlp_last_error.restype = C.c_char_p
+    L.lbm_copy_probe.argtypes = [vp, vp, sz, vp]
+    L.lbm_copy_probe.restype = C.c_int
     L.lbm_strerror.argtypes = [i]
     L.lbm_strerror.restype = C.c_char_p
     L.lbm_last_error.argtypes = [vp]
@@ -223,6 +226,17 @@ class Lbm:
         self._check(lib().lbm_set_rotor(self._ctx, rid, C.byref(d)))
         self._npts[rid] = d.n_blades * d.n_points
 
+    def set_inflow(self, mean, box=None, advect=0.0):
+        """mean: [3, nz, ny] inlet velocity; box: [3, lt, nz, ny] frozen
+        turbulence convected at `advect` cells per step (or None)."""
+        mean = _f64(mean).reshape(-1)
+        if box is None:
+            self._check(lib().lbm_set_inflow(self._ctx, _p(mean), None, 0, float(advect)))
+        else:
+            box = _f64(box)
+            lt = box.shape[1]
+            self._check(lib().lbm_set_inflow(self._ctx, _p(mean), _p(box.reshape(-1)), lt, float(advect)))
+
     def step(self, n=1):
         self._check(lib().lbm_step(self._ctx, int(n)))
 
@@ -293,6 +307,18 @@ class Lbm:
     def set_state(self, buf):
         buf = np.ascontiguousarray(buf, dtype=np.uint8)
         self._check(lib().lbm_set_state(self._ctx, C.c_void_p(buf.ctypes.data), buf.size))
+
+
+def copy_probe(src, dst, stream=None):
+    """Device copy src -> dst (torch CUDA tensors of equal byte size) with the
+    library's streaming copy kernel on `stream` (a torch stream)."""
+    nbytes = src.numel() * src.element_size()
+    assert dst.numel() * dst.element_size() == nbytes
+    h = stream.cuda_stream if stream is not None else None
+    rc = lib().lbm_copy_probe(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), nbytes,
+                              C.c_void_p(h) if h else None)
+    if rc != OK:
+        raise LbmError(rc, "copy probe failed")
 
 
 class MlpTrainer:

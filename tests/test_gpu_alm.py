@@ -90,3 +90,36 @@ def test_single_turbine_full_size_first_steps():
     assert err <= 1e-5
     T, Q, P = hist[-1][2]
     assert T > 0 and Q > 0  # the rotor is driven by the wind and thrusts downstream
+
+
+@pytest.mark.parametrize("storage,tol", [("f32", 2e-6)])
+def test_turbine_row_analogue_sheared_turbulent_inflow(storage, tol):
+    """Reduced turbine-row case: 96 x 32 x 32, ground wall (bounce-back), free-slip
+    top, sheared inflow plus a frozen turbulence box convected at the hub
+    speed, one rotor; populations and loads against the oracle for 12 steps."""
+    _need_gpu()
+    from paper_2402_13171_amd.lbm import Lbm
+    nx, ny, nz = 96, 32, 32
+    mean, box = workloads.turbine_row_inflow(ny=ny, nz=nz, hub_height=16.0, lt=32)
+    rot = workloads.make_rotor(hub=(24.0, 15.5, 15.5), radius=6.0, n_blades=3, n_points=8,
+                               tsr=7.0, u_ref=0.05)
+    sim = Lbm(nx, ny, nz, omega=1.9, storage=storage, bc_x="inout", bc_z=("noslip", "freeslip"))
+    ref = oracle.Grid(nx, ny, nz, omega=1.9, bc_x=oracle.INOUT, bc_zlo=oracle.NOSLIP,
+                      bc_zhi=oracle.FREESLIP)
+    u0 = np.broadcast_to(mean[:, :, :, None], (3, nz, ny, nx)).copy()
+    rho0 = np.ones((nz, ny, nx))
+    sim.init_fields(rho0, u0)
+    ref.init_fields(rho0, u0)
+    sim.set_inflow(mean, box, advect=0.05)
+    sim.set_rotor(0, rot)
+    ref.set_rotor(0, rot)
+    for t in range(12):
+        ref.set_inlet_plane(oracle.inflow_plane(mean, box, 0.05, t))
+        ref.step(1)
+        sim.step(1)
+        lg = sim.rotor_loads(0)
+        lr = ref.rotor_loads(0)
+        assert np.abs(lg - lr).max() <= 2e-5 * np.abs(lr).max(), t
+    err = np.abs(sim.pops() - ref.get_pops()).max()
+    print(f"turbine-row analogue ({storage}): max population error {err:.2e}")
+    assert err <= tol

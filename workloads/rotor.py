@@ -55,3 +55,20 @@ def turbine_row_rotors():
     return [make_rotor(hub=(x, 127.5, 127.5), radius=24.0, n_blades=3,
                        n_points=48, tsr=7.0, u_ref=0.05, eps=2.0)
             for x in (128.0, 368.0, 608.0)]
+
+
+def turbine_row_inflow(ny=256, nz=256, u_hub=0.05, hub_height=128.0, alpha=0.14,
+                       ti=0.05, seed=100, lt=256):
+    """Sheared inlet u(z) = u_hub ((z + 1/2) / hub_height)^alpha (height above
+    a ground wall at z = -1/2) plus a frozen random-phase turbulence box of
+    per-component rms ti * u_hub (same spectrum recipe, given seed), laid out
+    as box[3, lt, nz, ny] with lt the convected direction. Returns
+    (mean[3, nz, ny], box)."""
+    from .fields import random_phase_field
+    z = np.arange(nz, dtype=np.float64)
+    mean = np.zeros((3, nz, ny))
+    mean[0] = (u_hub * ((z + 0.5) / hub_height) ** alpha)[:, None]
+    n = max(lt, ny, nz)
+    _, u = random_phase_field(n, seed=seed, u_rms=ti * u_hub)
+    box = np.ascontiguousarray(u[:, :nz, :ny, :lt].transpose(0, 3, 1, 2))  # [3, x=lt, z, y]
+    return mean, box
