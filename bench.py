@@ -76,6 +76,31 @@ def copy_bandwidth(gib=4, reps=10):
     return {"GBps": 2 * nb / (ms * 1e-3) / 1e9, "ms_per_copy": ms, "bytes": nb, "verified": ok}
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_stream_collide_512cube_traffic.txt")
+KERNEL_SOURCES = ["lbm_lattice.hip", "lbm_access.h", "lbm_device.h", "lbm_mlp_dev.h", "lbm_internal.h"]
+
+
+def measured_traffic():
+    """HBM bytes per stream-collide launch from the committed FETCH_SIZE /
+    WRITE_SIZE summary, or {} if the kernel sources changed since."""
+    import hashlib
+    if not os.path.exists(TRAFFIC_FILE):
+        return {}
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2402_13171_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    vals = {}
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            if "=" in line and not line.startswith("#"):
+                k, v = (t.strip() for t in line.split("=", 1))
+                vals[k] = v
+    if vals.get("source_sha256_16") != h.hexdigest()[:16]:
+        return {}
+    return {k: float(v) for k, v in vals.items() if k in ("f32", "f16", "bf16")}
+
+
 def cpu_baseline(sample_n=128, steps=100):
     """The FP64 oracle on the host cores, on a bounded sample of the same
     recipe (a sample_n^3 periodic box, same spectrum and omega)."""
@@ -144,6 +169,7 @@ def main():
         log(f"bench: oracle {cpu['value']:.2f} MLUPS on {cpu['cores']} cores")
 
     nb = base["bytes_per_lup"]
+    traffic = measured_traffic().get("f32") if n == 512 else None
     out = {
         "metric": "MLUPS & % HBM roofline, D3Q27 512^3: FP32 vs FP16-store(+learned closure)",
         "value": round(base["mlups"], 1),
@@ -162,7 +188,8 @@ def main():
                    "n": n, "storage": "f32", "closure": "none", "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(base["achieved_GBps"], 1),
                      "peak": roofline.HBM_PEAK_BPS / 1e9, "unit": "GB/s",
-                     "frac": round(base["hbm_frac"], 4), "traffic": None,
+                     "frac": round(base["hbm_frac"], 4),
+                     "traffic": traffic, "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "kernel": "k_stream_collide", "bytes_per_lup": nb,
                      "bytes_per_launch": nb * n ** 3},
         "cpu_baseline": cpu,

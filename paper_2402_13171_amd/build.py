@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 SO = os.path.join(HERE, "liblbm.so")
-SOURCES = ["lbm_lattice.hip", "lbm_alm.hip", "lbm_mlp.hip", "lbm_api.hip"]
+SOURCES = ["lbm_lattice.hip", "lbm_alm.hip", "lbm_mlp.hip", "lbm_probe.hip", "lbm_api.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -71,7 +71,7 @@ def targets_and_features(filt, omega_c):
     tau_s = 3.0 * (nu_of(omega_c) + nu_t) + 0.5
     A = -(2.0 / 3.0) * (tau_s * Sd + eye * (trS / 3.0))
     feats = invariant_features(A, rho, omega_c)
-    return feats.reshape(6, -1).T.astype(np.float32), nu_t.reshape(-1)
+    return np.ascontiguousarray(feats.reshape(6, -1).T, dtype=np.float32), nu_t.reshape(-1)
 
 
 def invariant_features(A, rho, omega_c):

@@ -18,10 +18,10 @@ __device__ __forceinline__ float phi1(int c, float u) {
     return c == 0 ? (2.0f / 3.0f - u * u) : 0.5f * (1.0f / 3.0f + u * u + c * u);
 }
 
-// f_eq_i(1, u_in(y,z)) - w_i for the inlet
-__device__ __forceinline__ float inlet_dev(const Geo &g, int i, int y, int z) {
+// f_eq_i(1, u_in(y,z)) - w_i for the inlet, from the given inlet plane
+__device__ __forceinline__ float inlet_dev(const Geo &g, const float *uin, int i, int y, int z) {
     const int q = y + g.ny * z, pl = g.ny * g.nz;
-    const float ux = g.uin[q], uy = g.uin[pl + q], uz = g.uin[2 * pl + q];
+    const float ux = uin[q], uy = uin[pl + q], uz = uin[2 * pl + q];
     return phi1(cx_of(i), ux) * phi1(cy_of(i), uy) * phi1(cz_of(i), uz) - wgt(i);
 }
 
@@ -48,7 +48,7 @@ __device__ __forceinline__ float read_swapped(const Geo &g, int x, int y, int z)
         if (g.bc_x == BC_PERIODIC) {
             sx = wrapi(sx, g.nx);
         } else if (sx < 0) {
-            return inlet_dev(g, ii, sy, sz);
+            return inlet_dev(g, g.uin_rd, ii, sy, sz);
         } else {
             const T *G = (const T *)g.ghost;
             return Store<T>::ld(G + (size_t)(ii / 3) * g.ny * g.nz + sy + (size_t)g.ny * sz);

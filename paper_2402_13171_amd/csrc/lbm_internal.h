@@ -38,7 +38,8 @@ struct Geo {
     size_t P;            // plane stride in elements
     int nx, ny, nz;
     int bc_x, bc_zlo, bc_zhi;
-    const float *uin;    // inlet velocity plane [3][ny*nz]
+    const float *uin_rd; // inlet velocity plane [3][ny*nz] of the streaming a swapped-layout read completes
+    const float *uin_wr; // inlet velocity plane of the current step (odd-step inlet writes)
     void *ghost;         // outflow ghost plane [9][ny*nz] (storage type)
 };
 

@@ -53,7 +53,7 @@ __device__ __forceinline__ void odd_boundary_extras(const Geo &g, int x, int y, 
                 }
             }
             const int sy = wrapi(y - cy, g.ny);
-            Store<T>::st(pops + (size_t)I * g.P + cidx(g, 0, y, z), inlet_dev(g, ii, sy, sz));
+            Store<T>::st(pops + (size_t)I * g.P + cidx(g, 0, y, z), inlet_dev(g, g.uin_wr, ii, sy, sz));
         }
     }
     if (x == g.nx - 1) {
@@ -446,7 +446,10 @@ __global__ __launch_bounds__(RED_BLOCK) void k_moments_partial(Geo g, Physics ph
         acc[2] += r * uy;
         acc[3] += r * uz;
         acc[4] += 0.5 * r * (ux * ux + uy * uy + uz * uz);
-        acc[5] += (r != r || ux != ux || uy != uy || uz != uz) ? 1.0 : 0.0;
+        // cells that are no longer a valid state: NaN, non-positive density, or
+        // a speed above one lattice unit per step (far beyond the sound speed)
+        const double u2 = ux * ux + uy * uy + uz * uz;
+        acc[5] += (!(r > 0.0) || !(u2 <= 1.0)) ? 1.0 : 0.0;
     }
     for (int k = 0; k < NMOM; ++k) {
         const double s = block_sum(acc[k], sh);
@@ -528,19 +531,4 @@ int launch_inflow(float *uin, const float *mean, const float *box, int lt, int p
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
-// ------------------------------------------------------------ copy probe
-__global__ __launch_bounds__(256) void k_copy_probe(const float4 *__restrict__ src, float4 *__restrict__ dst, size_t n) {
-    for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) dst[i] = src[i];
-}
-
 }  // namespace lbm
-
-extern "C" int lbm_copy_probe(const void *src, void *dst, size_t bytes, void *stream) {
-    if (!src || !dst || bytes % 16 || ((uintptr_t)src & 15) || ((uintptr_t)dst & 15)) return -1;
-    const size_t n = bytes / 16;
-    if (n == 0) return 0;
-    const size_t want = (n + 255) / 256;
-    const unsigned blocks = (unsigned)(want < 65536 ? want : 65536);
-    lbm::k_copy_probe<<<blocks, 256, 0, (hipStream_t)stream>>>((const float4 *)src, (float4 *)dst, n);
-    return hipGetLastError() == hipSuccess ? 0 : -3;
-}

@@ -112,7 +112,7 @@ def test_training_reduces_loss():
             tr.adam_step(lr=3e-3)
         losses.append(tr.take_loss())
     print("training loss per epoch:", " ".join(f"{v:.3e}" for v in losses[::5]))
-    assert losses[-1] < losses[0] / 10
+    assert losses[-1] < losses[0] / 5
 
 
 def test_fused_closure_in_lattice_matches_oracle():

@@ -49,8 +49,12 @@ def oracle_window(rho, u, xyz, steps):
     return g.get_pops()[:, HALF, HALF, HALF]
 
 
-@pytest.mark.parametrize("storage,tol", [("f32", 1e-7), ("f16", 4e-5), ("bf16", 4e-4)])
-def test_512_sampled_cells_match_oracle(field, storage, tol):
+# tolerances: population rounding of the storage type over two steps; mass:
+# FP32 conserves to round-off, 16-bit storage drifts by the rounding of the
+# 27 n stored deviations per step (random walk)
+@pytest.mark.parametrize("storage,tol,mass_tol", [("f32", 1e-7, 1e-9), ("f16", 4e-5, 2e-8),
+                                                  ("bf16", 4e-4, 3e-7)])
+def test_512_sampled_cells_match_oracle(field, storage, tol, mass_tol):
     from paper_2402_13171_amd.lbm import Lbm
     import torch
     rho, u = field
@@ -68,11 +72,47 @@ def test_512_sampled_cells_match_oracle(field, storage, tol):
     sim.close()
     del sim
     torch.cuda.empty_cache()
-    assert abs(m2 - m0) <= 1e-9 * m0
     worst = 0.0
     for k, xyz in enumerate(cells):
         for steps in (1, 2):
             ref = oracle_window(rho, u, xyz, steps)
             worst = max(worst, np.abs(got[steps][k] - ref).max())
-    print(f"512^3 {storage}: worst population error over {len(cells)} cells = {worst:.3e}")
+    print(f"512^3 {storage}: worst population error over {len(cells)} cells = {worst:.3e}, "
+          f"relative mass drift {abs(m2 - m0) / m0:.2e}")
     assert worst <= tol
+    assert abs(m2 - m0) <= mass_tol * m0
+
+
+@pytest.fixture(scope="module")
+def c3_recipe_128():
+    """The bandwidth-bound recipe (random-phase spectrum k^4 exp(-2(k/8)^2),
+    u_rms 0.03, omega 1.9, 200 steps) on a periodic 128^3 box, run by the FP64
+    oracle (the 512^3 FP64 oracle needs tens of GB and ~15 min of host time)."""
+    _need_gpu()
+    n, steps = 128, 200
+    rho, u = workloads.random_phase_field(n, seed=0)
+    g = oracle.Grid(n, n, n, omega=1.9)
+    g.init_fields(rho, u)
+    g.step(steps)
+    return rho, u, g.fields()
+
+
+@pytest.mark.parametrize("storage,tol", [("f32", 1e-5), ("f16", 1e-3), ("bf16", None)])
+def test_storage_error_after_200_steps(c3_recipe_128, storage, tol):
+    """max relative velocity error of FP32 / FP16 / BF16 shifted storage against
+    the FP64 oracle; the FP16 gate is 1e-3, BF16 is reported."""
+    from paper_2402_13171_amd.lbm import Lbm
+    rho, u, (r_ref, u_ref) = c3_recipe_128
+    n = rho.shape[0]
+    sim = Lbm(n, n, n, omega=1.9, storage=storage)
+    sim.init_fields(rho, u)
+    sim.step(200)
+    r, ug = sim.fields()
+    err = np.linalg.norm(ug - u_ref, axis=0).max() / np.linalg.norm(u_ref, axis=0).max()
+    l2 = np.sqrt(((ug - u_ref) ** 2).sum() / (u_ref ** 2).sum())
+    rerr = np.abs(r - r_ref).max()
+    print(f"128^3 recipe, 200 steps, {storage}: eps_max {err:.3e}, L2 rel {l2:.3e}, max |drho| {rerr:.3e}")
+    if tol is not None:
+        assert err <= tol
+    else:
+        assert err < 0.1  # bfloat16: reported; sanity bound only
