@@ -51,6 +51,24 @@ def time_variant(n, rho, u, storage, closure, steps, warmup, blob=None):
     return {"mlups": mlups, "ms_per_step": ms / steps, "wall_s": wall, "mass": m, "ke": ke}
 
 
+def closure_weights():
+    """Trained closure weights if the training run has been committed, else a
+    seeded He-initialised network (the kernel's cost does not depend on the
+    weight values)."""
+    import numpy as np
+    path = os.path.join(ROOT, "results", "closure_weights.npy")
+    if os.path.exists(path):
+        return np.load(path).astype(np.float64), "results/closure_weights.npy"
+    rng = np.random.default_rng(0)
+    blob = np.zeros(1326)
+    blob[0:192] = rng.standard_normal(192) * np.sqrt(2.0 / 6.0)
+    blob[224:1248] = rng.standard_normal(1024) * np.sqrt(2.0 / 32.0)
+    blob[1280:1312] = rng.standard_normal(32) * np.sqrt(1.0 / 32.0)
+    blob[1319:1325] = 1e-3
+    blob[1325] = 1e-3
+    return blob, "seeded random network (no trained weights committed)"
+
+
 def copy_bandwidth(gib=4, reps=10):
     """Achievable HBM bandwidth: the library's streaming copy kernel over two
     gib-GiB buffers (bytes read + bytes written per second), as the paper
@@ -126,7 +144,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--n", type=int, default=512)
-    ap.add_argument("--variants", default="f32,f16,bf16,f32+smag")
+    ap.add_argument("--variants", default="f32,f16,bf16,f32+smag,f16+mlp")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -146,12 +164,14 @@ def main():
     cbw = copy_bandwidth()
     log(f"bench: copy probe {cbw['GBps']:.0f} GB/s")
 
+    blob, blob_src = closure_weights()
     results = {}
     for v in args.variants.split(","):
         storage, _, closure = v.partition("+")
         closure = closure or "none"
         log(f"bench: variant {v}: {args.warmup} warm-up + {args.steps} timed steps")
-        r = time_variant(n, rho, u, storage, closure, args.steps, args.warmup)
+        r = time_variant(n, rho, u, storage, closure, args.steps, args.warmup,
+                         blob=blob if closure == "mlp" else None)
         s_bytes = 4 if storage == "f32" else 2
         nb = roofline.bytes_per_lup(s_bytes)
         bw = roofline.achieved_bandwidth(r["mlups"] * 1e6, nb)
@@ -196,6 +216,7 @@ def main():
         "copy_probe": {"GBps": round(cbw["GBps"], 1), "bytes": cbw["bytes"],
                        "frac_of_peak": round(cbw["GBps"] * 1e9 / roofline.HBM_PEAK_BPS, 4),
                        "kernel_frac_of_copy": round(base["achieved_GBps"] / cbw["GBps"], 4)},
+        "closure_weights": blob_src,
         "variants": {k: {"mlups": round(v["mlups"], 1), "ms_per_step": round(v["ms_per_step"], 4),
                          "achieved_GBps": round(v["achieved_GBps"], 1),
                          "hbm_frac": round(v["hbm_frac"], 4), "bytes_per_lup": v["bytes_per_lup"],

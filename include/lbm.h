@@ -128,10 +128,11 @@ int lbm_set_rotor(lbm_ctx *ctx, int rotor_id, const lbm_rotor *rotor);
 int lbm_set_inflow(lbm_ctx *ctx, const double *mean, const double *box, int lt, double advect);
 
 /* Enqueue n time steps. With check_every > 0, an FP64 check runs every
- * check_every steps and at the end: it fails if the total mass drifts from its
- * value at the first checked call by more than 1e-6 (FP32 storage; 1e-5 FP16,
- * 1e-4 BF16) relative, or if any cell has a NaN, rho <= 0 or |u| > 1. The
- * call then synchronises and returns LBM_EUNSTABLE if a check failed. */
+ * check_every steps and at the end: it fails if any cell has a NaN, rho <= 0
+ * or |u| > 1, or, in a domain closed in x (periodic), if the total mass
+ * drifts from its value at the first checked call by more than 1e-6 (FP32
+ * storage; 1e-5 FP16, 1e-4 BF16) relative. The call then synchronises and
+ * returns LBM_EUNSTABLE if a check failed. */
 int lbm_step(lbm_ctx *ctx, int n);
 
 /* Density and velocity at the current time, u = (sum c f + F/2)/rho with

@@ -24,42 +24,47 @@ __device__ __forceinline__ double polar_lookup(double a, const RotorDev &R, cons
 
 __device__ __forceinline__ int wrap_any(int v, int n) { return ((v % n) + n) % n; }
 
-// one workgroup per rotor
+// Points are processed in batches of 32: workgroup (b, r) handles points
+// 32b .. 32b+31 of rotor r. Its 256 threads first stage the density and
+// velocity of the 8 cells around each of the 32 points in LDS (thread ->
+// point, corner), then 32 threads interpolate and evaluate the blade
+// elements. Each workgroup leaves FP64 partial thrust and torque; k_alm_loads
+// adds the partials in a fixed order.
+constexpr int ALM_BATCH = ALM_BLOCK / 8;
+constexpr int ALM_MAX_BATCHES = ALM_MAX_PTS / ALM_BATCH;
+
 template <typename T, int PAR>
 __global__ __launch_bounds__(ALM_BLOCK) void k_alm_points(Geo g, Physics ph, RotorDev *rots, long t) {
-    RotorDev &R = rots[blockIdx.x];
+    RotorDev &R = rots[blockIdx.y];
     const int npts = R.n_blades * R.n_points;
+    const int base = blockIdx.x * ALM_BATCH;
+    if (base >= npts) return;  // uniform across the workgroup
     __shared__ double s_corner[ALM_BLOCK][4];  // rho, u of one corner cell per work item
-    __shared__ double s_red[ALM_BLOCK][2];
-    double accT = 0.0, accQ = 0.0;
-
-    // points are processed in batches of ALM_BLOCK/8 (eight corner cells per point)
-    const int per_batch = ALM_BLOCK / 8;
-    for (int base = 0; base < npts; base += per_batch) {
-        // stage: thread -> (point, corner)
-        {
-            const int p = base + threadIdx.x / 8, corner = threadIdx.x % 8;
-            if (p < npts) {
-                const int b = p / R.n_points, k = p % R.n_points;
-                const double th = R.azimuth0 + R.omega_rot * (double)t + 2.0 * PI_D * b / R.n_blades;
-                const double rr = R.r[k];
-                const double xp[3] = {R.hub[0], R.hub[1] + rr * cos(th), R.hub[2] + rr * sin(th)};
-                const int dx = corner & 1, dy = (corner >> 1) & 1, dz = corner >> 2;
-                const int cx = wrap_any((int)floor(xp[0]) + dx, g.nx);
-                const int cy = wrap_any((int)floor(xp[1]) + dy, g.ny);
-                const int cz = wrap_any((int)floor(xp[2]) + dz, g.nz);
-                double r, ux, uy, uz;
-                cell_macro<T, PAR>(g, ph, ((size_t)cz * g.ny + cy) * g.nx + cx, cx, cy, cz, r, ux, uy, uz);
-                s_corner[threadIdx.x][0] = r;
-                s_corner[threadIdx.x][1] = ux;
-                s_corner[threadIdx.x][2] = uy;
-                s_corner[threadIdx.x][3] = uz;
-            }
+    __shared__ double s_red[ALM_BATCH][2];
+    {
+        const int p = base + threadIdx.x / 8, corner = threadIdx.x % 8;
+        if (p < npts) {
+            const int b = p / R.n_points, k = p % R.n_points;
+            const double th = R.azimuth0 + R.omega_rot * (double)t + 2.0 * PI_D * b / R.n_blades;
+            const double rr = R.r[k];
+            const double xp[3] = {R.hub[0], R.hub[1] + rr * cos(th), R.hub[2] + rr * sin(th)};
+            const int dx = corner & 1, dy = (corner >> 1) & 1, dz = corner >> 2;
+            const int cx = wrap_any((int)floor(xp[0]) + dx, g.nx);
+            const int cy = wrap_any((int)floor(xp[1]) + dy, g.ny);
+            const int cz = wrap_any((int)floor(xp[2]) + dz, g.nz);
+            double r, ux, uy, uz;
+            cell_macro<T, PAR>(g, ph, ((size_t)cz * g.ny + cy) * g.nx + cx, cx, cy, cz, r, ux, uy, uz);
+            s_corner[threadIdx.x][0] = r;
+            s_corner[threadIdx.x][1] = ux;
+            s_corner[threadIdx.x][2] = uy;
+            s_corner[threadIdx.x][3] = uz;
         }
-        __syncthreads();
-        // interpolate + blade element: one thread per point
-        if (threadIdx.x < per_batch && base + threadIdx.x < npts) {
-            const int p = base + threadIdx.x;
+    }
+    __syncthreads();
+    if (threadIdx.x < ALM_BATCH) {
+        double accT = 0.0, accQ = 0.0;
+        const int p = base + threadIdx.x;
+        if (p < npts) {
             const int b = p / R.n_points, k = p % R.n_points;
             const double th = R.azimuth0 + R.omega_rot * (double)t + 2.0 * PI_D * b / R.n_blades;
             const double ct = cos(th), st = sin(th);
@@ -67,16 +72,16 @@ __global__ __launch_bounds__(ALM_BLOCK) void k_alm_points(Geo g, Physics ph, Rot
             const double xp[3] = {R.hub[0], R.hub[1] + rr * ct, R.hub[2] + rr * st};
             double fr[3];
             for (int a = 0; a < 3; ++a) fr[a] = xp[a] - floor(xp[a]);
-            double s[4] = {0, 0, 0, 0};
+            double sm[4] = {0, 0, 0, 0};
             for (int c = 0; c < 8; ++c) {
                 const int dx = c & 1, dy = (c >> 1) & 1, dz = c >> 2;
                 const double w = (dx ? fr[0] : 1.0 - fr[0]) * (dy ? fr[1] : 1.0 - fr[1]) * (dz ? fr[2] : 1.0 - fr[2]);
-                for (int q = 0; q < 4; ++q) s[q] += w * s_corner[threadIdx.x * 8 + c][q];
+                for (int q = 0; q < 4; ++q) sm[q] += w * s_corner[threadIdx.x * 8 + c][q];
             }
-            const double rho = s[0];
+            const double rho = sm[0];
             // e_theta = (0, -sin, cos); relative in-plane wind W = W_n e_x - W_t e_theta
-            const double ut = -s[2] * st + s[3] * ct;
-            const double wn = s[1];
+            const double ut = -sm[2] * st + sm[3] * ct;
+            const double wn = sm[1];
             const double wt = -(ut - R.omega_rot * rr);
             double a = atan2(wn, wt) * (180.0 / PI_D) - R.twist[k] - R.pitch_deg;
             // |phi| <= 180 and |twist + pitch| < 180: one correction wraps to [-180, 180)
@@ -111,16 +116,15 @@ __global__ __launch_bounds__(ALM_BLOCK) void k_alm_points(Geo g, Physics ph, Rot
                 R.pt_force[3 * p + ax] = Fp[ax];
             }
             P[9] = (float)(1.0 / S);
-            accT += Fn;
-            accQ += rr * Ft;
+            accT = Fn;
+            accQ = rr * Ft;
         }
-        __syncthreads();
+        s_red[threadIdx.x][0] = accT;
+        s_red[threadIdx.x][1] = accQ;
     }
-    // deterministic FP64 tree reduction of thrust and torque
-    s_red[threadIdx.x][0] = accT;
-    s_red[threadIdx.x][1] = accQ;
     __syncthreads();
-    for (int s = ALM_BLOCK / 2; s > 0; s >>= 1) {
+    // deterministic FP64 tree over the batch
+    for (int s = ALM_BATCH / 2; s > 0; s >>= 1) {
         if (threadIdx.x < s) {
             s_red[threadIdx.x][0] += s_red[threadIdx.x + s][0];
             s_red[threadIdx.x][1] += s_red[threadIdx.x + s][1];
@@ -128,10 +132,24 @@ __global__ __launch_bounds__(ALM_BLOCK) void k_alm_points(Geo g, Physics ph, Rot
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        R.loads[0] = s_red[0][0];
-        R.loads[1] = s_red[0][1];
-        R.loads[2] = s_red[0][1] * R.omega_rot;
+        R.loads[3 + 2 * blockIdx.x] = s_red[0][0];
+        R.loads[4 + 2 * blockIdx.x] = s_red[0][1];
     }
+}
+
+// thrust, torque, power of each rotor from the batch partials, in batch order
+__global__ void k_alm_loads(RotorDev *rots) {
+    RotorDev &R = rots[blockIdx.x];
+    if (threadIdx.x != 0) return;
+    const int nb = (R.n_blades * R.n_points + ALM_BATCH - 1) / ALM_BATCH;
+    double T = 0.0, Q = 0.0;
+    for (int b = 0; b < nb; ++b) {
+        T += R.loads[3 + 2 * b];
+        Q += R.loads[4 + 2 * b];
+    }
+    R.loads[0] = T;
+    R.loads[1] = Q;
+    R.loads[2] = Q * R.omega_rot;
 }
 
 // Gather-form spreading over one rotor's box: F(X) = sum_p (-F_p) eta(X - x_p) / W_p
@@ -167,7 +185,13 @@ __global__ __launch_bounds__(ALM_BLOCK) void k_alm_spread(const RotorDev *rots, 
 template <typename T, int PAR>
 static void alm_t(const Geo &g, const Physics &ph, const RotorDev *h_rots, RotorDev *d_rots, int nrot, long t,
                   hipStream_t s) {
-    k_alm_points<T, PAR><<<nrot, ALM_BLOCK, 0, s>>>(g, ph, d_rots, t);
+    int nb = 1;
+    for (int r = 0; r < nrot; ++r) {
+        const int b = (h_rots[r].n_blades * h_rots[r].n_points + ALM_BATCH - 1) / ALM_BATCH;
+        nb = b > nb ? b : nb;
+    }
+    k_alm_points<T, PAR><<<dim3(nb, nrot), ALM_BLOCK, 0, s>>>(g, ph, d_rots, t);
+    k_alm_loads<<<nrot, 64, 0, s>>>(d_rots);
     for (int r = 0; r < nrot; ++r) {
         const size_t nb = (size_t)h_rots[r].box.bnx * h_rots[r].box.bny * h_rots[r].box.bnz;
         k_alm_spread<<<(unsigned)((nb + ALM_BLOCK - 1) / ALM_BLOCK), ALM_BLOCK, 0, s>>>(d_rots, r);

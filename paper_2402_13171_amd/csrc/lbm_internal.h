@@ -64,7 +64,7 @@ struct RotorDev {
     // outputs
     float *pts;        // per point: x[3], F[3] (force on blade), c0[3] (as float), inv W
     double *pt_force;  // per point: F[3] in FP64
-    double *loads;     // T, Q, P
+    double *loads;     // T, Q, P, then per batch of 32 points: partial T, Q
     // spreading box
     ForceBox box;
     float *Fbox;
@@ -95,6 +95,7 @@ int launch_check(int storage, int parity, const Geo &g, const Physics &ph, doubl
 int launch_alm(int storage, int parity, const Geo &g, const Physics &ph, const RotorDev *h_rots,
                RotorDev *d_rots, int nrot, long t, hipStream_t s);
 constexpr int ALM_MAX_POINTS = 512;
+constexpr int ALM_LOADS_LEN = 3 + 2 * (ALM_MAX_POINTS / 32);
 constexpr int RED_NBLOCKS = 1024;   // reduction grid (fixed: deterministic sums)
 constexpr int RED_NMOM = 6;
 

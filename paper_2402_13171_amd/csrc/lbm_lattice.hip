@@ -88,13 +88,17 @@ __device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned total) {
     return xcd < r ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
 }
 
-// One workgroup = one tile of 64 (x) by 4 (y) cells in one z plane; a wave
-// is one 64-cell row segment.
+// One workgroup of 256 threads = one tile of tw (x) by 256/tw (y) cells in one
+// z plane, tw in {64, 128, 256}; a wave is a 64-cell row segment. Wide tiles
+// keep the cache lines that odd-step shifted accesses split between
+// neighbouring row segments inside one workgroup.
 template <typename T, int PAR, int CL, bool BCG, bool FRC>
-__global__ __launch_bounds__(256) void k_stream_collide(Geo g, Physics ph, unsigned gx, unsigned gy, unsigned total) {
+__global__ __launch_bounds__(256) void k_stream_collide(Geo g, Physics ph, unsigned gx, unsigned gy, unsigned total,
+                                                        unsigned tw_log2) {
     const unsigned tile = xcd_tile(blockIdx.x, total);
-    const int x = (int)(tile % gx) * 64 + threadIdx.x;
-    const int y = (int)((tile / gx) % gy) * 4 + threadIdx.y;
+    const unsigned tw = 1u << tw_log2, th = 256u >> tw_log2;
+    const int x = (int)((tile % gx) * tw + (threadIdx.x & (tw - 1)));
+    const int y = (int)(((tile / gx) % gy) * th + (threadIdx.x >> tw_log2));
     const int z = (int)(tile / (gx * gy));
     // the learned closure runs on the matrix cores, which need every lane of
     // the wave: out-of-range lanes then compute on a rest state and store nothing
@@ -162,14 +166,16 @@ __global__ __launch_bounds__(256) void k_stream_collide(Geo g, Physics ph, unsig
 // ------------------------------------------------------------ dispatch
 template <typename T, int PAR, int CL>
 static void launch_sc(bool bcg, bool frc, const Geo &g, const Physics &ph, hipStream_t s) {
-    const unsigned gx = (g.nx + 63) / 64, gy = (g.ny + 3) / 4, total = gx * gy * (unsigned)g.nz;
-    dim3 blk(64, 4, 1), grd(total, 1, 1);
+    const unsigned twl = g.nx >= 256 ? 8u : (g.nx >= 128 ? 7u : 6u);
+    const unsigned tw = 1u << twl, th = 256u >> twl;
+    const unsigned gx = (g.nx + tw - 1) / tw, gy = (g.ny + th - 1) / th, total = gx * gy * (unsigned)g.nz;
+    dim3 blk(256, 1, 1), grd(total, 1, 1);
     if (bcg) {
-        if (frc) k_stream_collide<T, PAR, CL, true, true><<<grd, blk, 0, s>>>(g, ph, gx, gy, total);
-        else k_stream_collide<T, PAR, CL, true, false><<<grd, blk, 0, s>>>(g, ph, gx, gy, total);
+        if (frc) k_stream_collide<T, PAR, CL, true, true><<<grd, blk, 0, s>>>(g, ph, gx, gy, total, twl);
+        else k_stream_collide<T, PAR, CL, true, false><<<grd, blk, 0, s>>>(g, ph, gx, gy, total, twl);
     } else {
-        if (frc) k_stream_collide<T, PAR, CL, false, true><<<grd, blk, 0, s>>>(g, ph, gx, gy, total);
-        else k_stream_collide<T, PAR, CL, false, false><<<grd, blk, 0, s>>>(g, ph, gx, gy, total);
+        if (frc) k_stream_collide<T, PAR, CL, false, true><<<grd, blk, 0, s>>>(g, ph, gx, gy, total, twl);
+        else k_stream_collide<T, PAR, CL, false, false><<<grd, blk, 0, s>>>(g, ph, gx, gy, total, twl);
     }
 }
 

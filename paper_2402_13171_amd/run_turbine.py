@@ -1,0 +1,156 @@
+"""Wind-turbine runs of the actuator-line path.
+
+    python -m paper_2402_13171_amd.run_turbine single --out results/single_turbine.json
+    python -m paper_2402_13171_amd.run_turbine row --weights results/closure_weights.npy \
+        --out results/turbine_row.json
+
+single: 256 x 128 x 128, FP32, uniform inflow 0.05 at x = 0, zero-gradient
+outflow, periodic y/z, one 3-blade rotor (diameter 32, TSR 7, 3 x 32 points,
+Gaussian eps = 2) at x = 64, 2000 steps. Reports MLUPS with the rotor and
+without it (the paper's way of isolating the turbine overhead, Sec. 4.3,
+Table 1), the thrust/torque/power time series, and the final normal and
+tangential force per blade point.
+
+row: 1024 x 256 x 256, FP16 storage, learned closure, three rotors of
+diameter 48 spaced 5 D apart, ground wall (bounce-back) and free-slip top,
+sheared inflow u = 0.05 ((z + 1/2)/128)^0.14 plus a convected frozen
+turbulence box (5 % intensity), 5000 steps; per-rotor thrust and power.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+import workloads
+from .lbm import Lbm
+
+
+def timed_steps(sim, n):
+    import torch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(sim.stream)
+    sim.step(n)
+    e1.record(sim.stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / n
+
+
+def single(args, log):
+    nx, ny, nz = 256, 128, 128
+    rot = workloads.single_turbine_rotor()
+    u0 = np.zeros((3, nz, ny, nx))
+    u0[0] = 0.05
+    out = {"workload": "single turbine 256x128x128 FP32, inflow 0.05, rotor D=32 TSR 7, eps 2"}
+    # without the rotor
+    sim = Lbm(nx, ny, nz, omega=args.omega, bc_x="inout", u_in=(0.05, 0, 0))
+    sim.init_fields(np.ones((nz, ny, nx)), u0)
+    sim.step(10)
+    ms0 = timed_steps(sim, 200)
+    sim.close()
+    # with the rotor
+    sim = Lbm(nx, ny, nz, omega=args.omega, bc_x="inout", u_in=(0.05, 0, 0))
+    sim.init_fields(np.ones((nz, ny, nx)), u0)
+    sim.set_rotor(0, rot)
+    series = []
+    t0 = time.time()
+    chunk = 10
+    ms_rot = []
+    while sim.time < args.steps:
+        ms_rot.append(timed_steps(sim, chunk))
+        T, Q, P = sim.rotor_loads(0)
+        series.append([sim.time, T, Q, P])
+        if sim.time % 500 == 0:
+            log(f"single turbine: step {sim.time}, T {T:.4e}, P {P:.4e}")
+    loads, pts = sim.rotor_loads(0, with_points=True)
+    n = nx * ny * nz
+    per_rev = int(round(2 * np.pi / rot["omega_rot"]))
+    s = np.array(series)
+    last = s[s[:, 0] > s[-1, 0] - per_rev]
+    # normal (axial) and tangential force per point along blade 0
+    npb = len(rot["r"])
+    th = rot["azimuth0"] + rot["omega_rot"] * (sim.time - 1)
+    et = np.array([0.0, -np.sin(th), np.cos(th)])
+    out.update({
+        "steps": sim.time, "mlups_without_rotor": n / (ms0 * 1e-3) / 1e6,
+        "mlups_with_rotor": n / (np.median(ms_rot) * 1e-3) / 1e6,
+        "turbine_overhead_pct": 100.0 * (np.median(ms_rot) - ms0) / ms0,
+        "mean_last_revolution": {"thrust": float(last[:, 1].mean()), "torque": float(last[:, 2].mean()),
+                                 "power": float(last[:, 3].mean())},
+        "series_every_10_steps": s.tolist(),
+        "blade0_points": {"r": list(map(float, rot["r"])), "normal": pts[:npb, 0].tolist(),
+                          "tangential": (pts[:npb] @ et).tolist()},
+        "wall_s": time.time() - t0,
+    })
+    sim.close()
+    return out
+
+
+def row(args, log):
+    nx, ny, nz = 1024, 256, 256
+    rots = workloads.turbine_row_rotors()
+    mean, box = workloads.turbine_row_inflow(ny=ny, nz=nz)
+    blob = np.load(args.weights).astype(np.float64) if args.weights else None
+    closure = "mlp" if blob is not None else "smag"
+    sim = Lbm(nx, ny, nz, omega=args.omega, storage="f16", closure=closure, cs_smag=0.1, bc_x="inout",
+              bc_z=("noslip", "freeslip"), check_every=500)
+    if blob is not None:
+        sim.set_closure_weights(blob)
+    u0 = np.broadcast_to(mean[:, :, :, None], (3, nz, ny, nx)).astype(np.float64)
+    sim.init_fields(np.ones((nz, ny, nx)), u0)
+    del u0
+    sim.set_inflow(mean, box, advect=0.05)
+    for k, r in enumerate(rots):
+        sim.set_rotor(k, r)
+    series = []
+    ms = []
+    t0 = time.time()
+    while sim.time < args.steps:
+        ms.append(timed_steps(sim, 50))
+        series.append([sim.time] + [float(v) for k in range(3) for v in sim.rotor_loads(k)])
+        if sim.time % 500 == 0:
+            log(f"turbine row: step {sim.time}, thrusts " + " ".join(f"{series[-1][1 + 3 * k]:.3e}" for k in range(3)))
+    s = np.array(series)
+    per_rev = int(round(2 * np.pi / rots[0]["omega_rot"]))
+    last = s[s[:, 0] > s[-1, 0] - 2 * per_rev]
+    n = nx * ny * nz
+    out = {
+        "workload": "turbine row 1024x256x256 FP16 + " + closure + " closure, 3 rotors D=48, sheared turbulent inflow",
+        "steps": sim.time, "mlups": n / (np.median(ms) * 1e-3) / 1e6,
+        "per_rotor_mean_last_two_revolutions": [
+            {"thrust": float(last[:, 1 + 3 * k].mean()), "torque": float(last[:, 2 + 3 * k].mean()),
+             "power": float(last[:, 3 + 3 * k].mean())} for k in range(3)],
+        "series_every_50_steps": s.tolist(), "wall_s": time.time() - t0,
+    }
+    sim.close()
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("case", choices=["single", "row"])
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--omega", type=float, default=1.9)
+    ap.add_argument("--weights", default=None)
+    ap.add_argument("--out", default=None)
+    a = ap.parse_args(argv)
+    if a.steps is None:
+        a.steps = 2000 if a.case == "single" else 5000
+    t_start = time.time()
+    log = lambda *m: print(f"[{time.time() - t_start:7.1f}s]", *m, flush=True)
+    res = single(a, log) if a.case == "single" else row(a, log)
+    out = a.out or f"results/{'single_turbine' if a.case == 'single' else 'turbine_row'}.json"
+    os.makedirs(os.path.dirname(out) or ".", exist_ok=True)
+    with open(out, "w") as fh:
+        json.dump(res, fh)
+    log("written", out, {k: v for k, v in res.items() if not isinstance(v, (list, dict))})
+    return res
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])

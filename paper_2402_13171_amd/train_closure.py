@@ -86,7 +86,8 @@ def main(argv=None):
             E = spec.get(s // w)
             errs[str(s // w)] = ct.spectrum_error(E, Eref[s], kmax) if E is not None and np.all(np.isfinite(E)) else None
         ke = {str(s // w): float(spec[s // w][1:].sum()) if s // w in spec else None for s in evals}
-        results[closure] = {"spectrum_log_error": errs, "resolved_ke": ke}
+        results[closure] = {"spectrum_log_error": errs, "resolved_ke": ke,
+                            "spectra": {str(k): v[:kmax + 1].tolist() for k, v in spec.items()}}
         log(f"LES {closure}: log-spectrum error {errs}")
     ke_ref = {str(s // w): float(Eref[s][1:].sum()) for s in evals}
     last = str(coarse_steps[-1])
@@ -100,6 +101,7 @@ def main(argv=None):
         "training_cells": int(feats.shape[0]), "epochs": a.epochs,
         "loss_per_epoch": losses, "a_priori_corr": {"mlp": corr_mlp, "smag": corr_smag},
         "kmax": kmax, "les": results, "reference_resolved_ke": ke_ref,
+        "reference_spectra": {str(s // w): Eref[s][:kmax + 1].tolist() for s in evals},
         "gain_error_ratio_at_last_step": gain, "wall_s": time.time() - t_start,
     }
     os.makedirs(os.path.dirname(a.out) or ".", exist_ok=True)
