@@ -65,7 +65,9 @@ typedef struct {
     int nx, ny, nz;        /* cells; each >= 2, nx*ny*nz < 2^32 */
     double omega;          /* shear relaxation rate omega_1, 0 < omega < 2 */
     double omega_hi[9];    /* omega_2..omega_10 (bulk, 3rd..6th order); an
-                              entry of 0 means the default 1.0 */
+                              entry of 0 means the default 1.0. With all of
+                              omega_3..omega_10 at 1 the collision takes a
+                              shorter exact form (higher cumulants vanish) */
     int storage;           /* lbm_storage: populations are stored as the
                               deviation f_i - w_i in this type */
     int closure;           /* lbm_closure */

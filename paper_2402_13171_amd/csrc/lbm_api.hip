@@ -41,6 +41,8 @@ struct lbm_ctx {
     long t = 0;
     int parity = 0;
     float omega2 = 1.0f;
+    float omega_hi[8] = {1, 1, 1, 1, 1, 1, 1, 1};  // omega_3 .. omega_10
+    bool general_rates = false;
     float *d_ffield = nullptr;
     RotorHost rot[MAX_ROTORS];
     RotorDev *d_rots = nullptr;  // compacted active rotors
@@ -114,6 +116,7 @@ Physics physics_of(const lbm_ctx *c) {
     ph.tau0 = (float)(1.0 / c->cfg.omega);
     ph.smag_c = (float)(18.0 * std::sqrt(2.0) * c->cfg.cs_smag * c->cfg.cs_smag);
     ph.nu0 = (float)((1.0 / c->cfg.omega - 0.5) / 3.0);
+    for (int k = 0; k < 8; ++k) ph.omega_hi[k] = c->omega_hi[k];
     for (int k = 0; k < 3; ++k) ph.bf[k] = (float)c->cfg.body_force[k];
     ph.ffield = c->d_ffield;
     ph.nbox = (int)c->h_rots.size();
@@ -235,8 +238,6 @@ int lbm_create(const lbm_config *cfg, lbm_ctx **out) {
     if (!(c.omega > 0.0 && c.omega < 2.0)) return LBM_EINVAL;
     for (int k = 0; k < 9; ++k)
         if (!(c.omega_hi[k] >= 0.0 && c.omega_hi[k] < 2.0)) return LBM_EINVAL;
-    for (int k = 1; k < 9; ++k)  // omega_3..omega_10: the device collision assumes the default 1
-        if (c.omega_hi[k] != 0.0 && c.omega_hi[k] != 1.0) return LBM_EINVAL;
     if (c.storage < LBM_F32 || c.storage > LBM_BF16) return LBM_EINVAL;
     if (c.closure < LBM_CLOSURE_NONE || c.closure > LBM_CLOSURE_MLP) return LBM_EINVAL;
     if (c.closure == LBM_CLOSURE_SMAG && !(c.cs_smag >= 0.0)) return LBM_EINVAL;
@@ -254,6 +255,10 @@ int lbm_create(const lbm_config *cfg, lbm_ctx **out) {
     x->P = round_up(n * x->esize, 256) / x->esize;
     x->pop_bytes = 27 * x->P * x->esize;
     x->omega2 = c.omega_hi[0] == 0.0 ? 1.0f : (float)c.omega_hi[0];
+    for (int k = 0; k < 8; ++k) {
+        x->omega_hi[k] = c.omega_hi[k + 1] == 0.0 ? 1.0f : (float)c.omega_hi[k + 1];
+        if (x->omega_hi[k] != 1.0f) x->general_rates = true;
+    }
     const size_t plane = (size_t)c.ny * c.nz;
     x->off_ghost = 0;
     x->off_uin = round_up(9 * plane * x->esize, 256);
@@ -513,7 +518,7 @@ int lbm_step(lbm_ctx *c, int nsteps) {
         g = geo_of(c);
         if (nrot > 0 && launch_alm(st, c->parity, g, ph, c->h_rots.data(), c->d_rots, nrot, c->t, c->stream))
             return fail(c, LBM_EHIP, "actuator-line launch failed");
-        if (launch_stream_collide(st, c->parity, (int)c->cfg.closure, bcg, frc, g, ph, c->stream))
+        if (launch_stream_collide(st, c->parity, (int)c->cfg.closure, bcg, frc, c->general_rates, g, ph, c->stream))
             return fail(c, LBM_EHIP, "stream-collide launch failed");
         c->parity ^= 1;
         c->t += 1;

@@ -218,4 +218,159 @@ __device__ __forceinline__ void collide_unit_rates(const CellMoments &m, float o
     for (int i = 0; i < 27; ++i) out[i] = k[i];
 }
 
+// ------------------------------------------------------------ general rates
+// Collision with arbitrary omega_3..omega_10: the pre-collision cumulants of
+// third to sixth order are needed. Central moments of f about u are those of
+// the deviations (forward passes on d) plus those of the weights, the
+// product of (1, -u, 1/3 + u^2) per axis; cumulants use k = kappa / rho with
+// the zero-mean set-partition formulas; after relaxation the moments are
+// rebuilt order by order and the weight moments subtracted again before the
+// inverse transform, so the output is d* = f* - w.
+__device__ __forceinline__ void fwd_triple(float &a, float &b, float &c, float u) {
+    const float fm = a, f0 = b, fp = c;
+    const float k0 = fm + f0 + fp;
+    const float dpm = fp - fm;
+    b = fmaf(-u, k0, dpm);
+    c = fmaf(u * u, k0, fmaf(-2.0f * u, dpm, fp + fm));
+    a = k0;
+}
+
+__device__ __forceinline__ void collide_general(const float d[27], const CellMoments &m, float omega1, float omega2,
+                                                const float *wh, float Fx, float Fy, float Fz, float out[27]) {
+    const float ux = m.ux, uy = m.uy, uz = m.uz;
+    float k[27];
+#pragma unroll
+    for (int i = 0; i < 27; ++i) k[i] = d[i];
+#pragma unroll
+    for (int p = 0; p < 9; ++p) fwd_triple(k[p], k[p + 9], k[p + 18], uz);
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int ix = 0; ix < 3; ++ix) fwd_triple(k[ix + 9 * c], k[ix + 9 * c + 3], k[ix + 9 * c + 6], uy);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) fwd_triple(k[3 * q], k[3 * q + 1], k[3 * q + 2], ux);
+    // weight moments about u
+    const float mx[3] = {1.0f, -ux, 1.0f / 3.0f + ux * ux};
+    const float my[3] = {1.0f, -uy, 1.0f / 3.0f + uy * uy};
+    const float mz[3] = {1.0f, -uz, 1.0f / 3.0f + uz * uz};
+    float kw[27];
+#pragma unroll
+    for (int i = 0; i < 27; ++i) kw[i] = mx[i % 3] * my[(i / 3) % 3] * mz[i / 9];
+    const float rho = m.rho, ir = 1.0f / rho;
+    float n[27];  // normalised moments of f (orders >= 2)
+#pragma unroll
+    for (int i = 0; i < 27; ++i) n[i] = (kw[i] + k[i]) * ir;
+#define N(a, b, c) n[(a) + 3 * (b) + 9 * (c)]
+    // second order deviations from 1/3 on the diagonal use the accurate forms
+    const float exx = m.ex, eyy = m.ey, ezz = m.ez;
+    N(2, 0, 0) = 1.0f / 3.0f + exx;
+    N(0, 2, 0) = 1.0f / 3.0f + eyy;
+    N(0, 0, 2) = 1.0f / 3.0f + ezz;
+    N(1, 1, 0) = m.kxy;
+    N(1, 0, 1) = m.kxz;
+    N(0, 1, 1) = m.kyz;
+    // cumulants (orders 4..6 subtract the set-partition products)
+    const float c220 = N(2, 2, 0) - (N(2, 0, 0) * N(0, 2, 0) + 2.0f * N(1, 1, 0) * N(1, 1, 0));
+    const float c202 = N(2, 0, 2) - (N(2, 0, 0) * N(0, 0, 2) + 2.0f * N(1, 0, 1) * N(1, 0, 1));
+    const float c022 = N(0, 2, 2) - (N(0, 2, 0) * N(0, 0, 2) + 2.0f * N(0, 1, 1) * N(0, 1, 1));
+    const float c211 = N(2, 1, 1) - (N(2, 0, 0) * N(0, 1, 1) + 2.0f * N(1, 1, 0) * N(1, 0, 1));
+    const float c121 = N(1, 2, 1) - (N(0, 2, 0) * N(1, 0, 1) + 2.0f * N(1, 1, 0) * N(0, 1, 1));
+    const float c112 = N(1, 1, 2) - (N(0, 0, 2) * N(1, 1, 0) + 2.0f * N(1, 0, 1) * N(0, 1, 1));
+    const float c221 = N(2, 2, 1) - (N(2, 0, 0) * N(0, 2, 1) + N(0, 2, 0) * N(2, 0, 1) + 4.0f * N(1, 1, 0) * N(1, 1, 1) +
+                                     2.0f * N(1, 0, 1) * N(1, 2, 0) + 2.0f * N(0, 1, 1) * N(2, 1, 0));
+    const float c212 = N(2, 1, 2) - (N(2, 0, 0) * N(0, 1, 2) + N(0, 0, 2) * N(2, 1, 0) + 4.0f * N(1, 0, 1) * N(1, 1, 1) +
+                                     2.0f * N(1, 1, 0) * N(1, 0, 2) + 2.0f * N(0, 1, 1) * N(2, 0, 1));
+    const float c122 = N(1, 2, 2) - (N(0, 2, 0) * N(1, 0, 2) + N(0, 0, 2) * N(1, 2, 0) + 4.0f * N(0, 1, 1) * N(1, 1, 1) +
+                                     2.0f * N(1, 1, 0) * N(0, 1, 2) + 2.0f * N(1, 0, 1) * N(0, 2, 1));
+    auto s42 = [&](const float *q) {
+        return q[2] * q[24] + q[6] * q[20] + q[18] * q[8] +
+               4.0f * (q[4] * q[22] + q[10] * q[16] + q[12] * q[14]);
+    };
+    auto s33 = [&](const float *q) {
+        // 4 k111^2 + 2 (k210 k012 + k201 k021 + k120 k102)
+        return 4.0f * q[13] * q[13] + 2.0f * (q[5] * q[21] + q[11] * q[15] + q[7] * q[19]);
+    };
+    auto s222 = [&](const float *q) {
+        return q[2] * q[6] * q[18] + 2.0f * (q[2] * q[12] * q[12] + q[6] * q[10] * q[10] + q[18] * q[4] * q[4]) +
+               8.0f * q[4] * q[10] * q[12];
+    };
+    const float c222 = N(2, 2, 2) - s42(n) - s33(n) + 2.0f * s222(n);
+    // relaxation (omega_3..omega_10 in wh[0..7])
+    const float s1 = 1.0f - omega1;
+    float r[27];
+#pragma unroll
+    for (int i = 0; i < 27; ++i) r[i] = 0.0f;
+#define R(a, b, c) r[(a) + 3 * (b) + 9 * (c)]
+    {
+        const float dxy = s1 * (exx - eyy), dxz = s1 * (exx - ezz), trd = (1.0f - omega2) * (exx + eyy + ezz);
+        R(2, 0, 0) = 1.0f / 3.0f + (trd + dxy + dxz) * (1.0f / 3.0f);
+        R(0, 2, 0) = 1.0f / 3.0f + (trd - 2.0f * dxy + dxz) * (1.0f / 3.0f);
+        R(0, 0, 2) = 1.0f / 3.0f + (trd + dxy - 2.0f * dxz) * (1.0f / 3.0f);
+        R(1, 1, 0) = s1 * m.kxy;
+        R(1, 0, 1) = s1 * m.kxz;
+        R(0, 1, 1) = s1 * m.kyz;
+    }
+    {
+        const float a3 = 1.0f - wh[0], a4 = 1.0f - wh[1];
+        // pairs (120, 102), (210, 012), (201, 021): sums with omega_3, differences with omega_4
+        const int p0[3] = {1 + 3 * 2, 2 + 3 * 1, 2 + 9 * 1};
+        const int p1[3] = {1 + 9 * 2, 3 * 1 + 9 * 2, 3 * 2 + 9 * 1};
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const float sm = a3 * (n[p0[q]] + n[p1[q]]);
+            const float df = a4 * (n[p0[q]] - n[p1[q]]);
+            r[p0[q]] = 0.5f * (sm + df);
+            r[p1[q]] = 0.5f * (sm - df);
+        }
+        R(1, 1, 1) = (1.0f - wh[2]) * N(1, 1, 1);
+    }
+    float C220, C202, C022;
+    {
+        const float a6 = 1.0f - wh[3], a7 = 1.0f - wh[4];
+        const float A = a6 * (c220 - 2.0f * c202 + c022), B = a6 * (c220 + c202 - 2.0f * c022);
+        const float S = a7 * (c220 + c202 + c022);
+        C220 = (S + A + B) * (1.0f / 3.0f);
+        C202 = (S - A) * (1.0f / 3.0f);
+        C022 = (S - B) * (1.0f / 3.0f);
+    }
+    const float a8 = 1.0f - wh[5], a9 = 1.0f - wh[6], a10 = 1.0f - wh[7];
+    // rebuild post-collision normalised moments, lower orders first
+    R(2, 2, 0) = C220 + R(2, 0, 0) * R(0, 2, 0) + 2.0f * R(1, 1, 0) * R(1, 1, 0);
+    R(2, 0, 2) = C202 + R(2, 0, 0) * R(0, 0, 2) + 2.0f * R(1, 0, 1) * R(1, 0, 1);
+    R(0, 2, 2) = C022 + R(0, 2, 0) * R(0, 0, 2) + 2.0f * R(0, 1, 1) * R(0, 1, 1);
+    R(2, 1, 1) = a8 * c211 + R(2, 0, 0) * R(0, 1, 1) + 2.0f * R(1, 1, 0) * R(1, 0, 1);
+    R(1, 2, 1) = a8 * c121 + R(0, 2, 0) * R(1, 0, 1) + 2.0f * R(1, 1, 0) * R(0, 1, 1);
+    R(1, 1, 2) = a8 * c112 + R(0, 0, 2) * R(1, 1, 0) + 2.0f * R(1, 0, 1) * R(0, 1, 1);
+    R(2, 2, 1) = a9 * c221 + R(2, 0, 0) * R(0, 2, 1) + R(0, 2, 0) * R(2, 0, 1) + 4.0f * R(1, 1, 0) * R(1, 1, 1) +
+                 2.0f * R(1, 0, 1) * R(1, 2, 0) + 2.0f * R(0, 1, 1) * R(2, 1, 0);
+    R(2, 1, 2) = a9 * c212 + R(2, 0, 0) * R(0, 1, 2) + R(0, 0, 2) * R(2, 1, 0) + 4.0f * R(1, 0, 1) * R(1, 1, 1) +
+                 2.0f * R(1, 1, 0) * R(1, 0, 2) + 2.0f * R(0, 1, 1) * R(2, 0, 1);
+    R(1, 2, 2) = a9 * c122 + R(0, 2, 0) * R(1, 0, 2) + R(0, 0, 2) * R(1, 2, 0) + 4.0f * R(0, 1, 1) * R(1, 1, 1) +
+                 2.0f * R(1, 1, 0) * R(0, 1, 2) + 2.0f * R(1, 0, 1) * R(0, 2, 1);
+    R(2, 2, 2) = a10 * c222 + s42(r) + s33(r) - 2.0f * s222(r);
+    // kappa* - kappa_w: orders >= 2 as rho r - kw; order 0 and 1 directly
+#pragma unroll
+    for (int i = 0; i < 27; ++i) k[i] = rho * r[i] - kw[i];
+    k[0] = m.drho;
+    k[1] = 0.5f * Fx + ux;
+    k[3] = 0.5f * Fy + uy;
+    k[9] = 0.5f * Fz + uz;
+    // the second-order diagonal in its accurate form: rho (1/3 + e*) - (1/3 + u^2)
+    k[2] = m.drho * (1.0f / 3.0f) + rho * (R(2, 0, 0) - 1.0f / 3.0f) - ux * ux;
+    k[6] = m.drho * (1.0f / 3.0f) + rho * (R(0, 2, 0) - 1.0f / 3.0f) - uy * uy;
+    k[18] = m.drho * (1.0f / 3.0f) + rho * (R(0, 0, 2) - 1.0f / 3.0f) - uz * uz;
+#undef N
+#undef R
+#pragma unroll
+    for (int q = 0; q < 9; ++q) inv_triple(k[3 * q], k[3 * q + 1], k[3 * q + 2], ux);
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int ix = 0; ix < 3; ++ix) inv_triple(k[ix + 9 * c], k[ix + 9 * c + 3], k[ix + 9 * c + 6], uy);
+#pragma unroll
+    for (int p = 0; p < 9; ++p) inv_triple(k[p], k[p + 9], k[p + 18], uz);
+#pragma unroll
+    for (int i = 0; i < 27; ++i) out[i] = k[i];
+}
+
 }  // namespace lbm

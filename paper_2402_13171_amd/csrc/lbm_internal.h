@@ -46,6 +46,7 @@ struct Geo {
 struct Physics {
     float omega, omega2, tau0, smag_c;  // smag_c = 18 sqrt(2) Cs^2
     float nu0;
+    float omega_hi[8];                  // omega_3 .. omega_10 (general-rate collision)
     float bf[3];                        // uniform body force
     const float *ffield;                // dense force [3][n] or null
     int nbox;
@@ -74,7 +75,7 @@ constexpr int PT_STRIDE = 10;
 
 // Kernel launchers (defined in the .hip files).
 int launch_stream_collide(int storage, int parity, int closure, bool general_bc, bool force,
-                          const Geo &g, const Physics &ph, hipStream_t s);
+                          bool general_rates, const Geo &g, const Physics &ph, hipStream_t s);
 int launch_init_tgv(int storage, const Geo &g, double u0, double k, double rho0, hipStream_t s);
 int launch_init_eq(int storage, const Geo &g, const double *rho, const double *u, size_t cell0,
                    size_t ncell, hipStream_t s);

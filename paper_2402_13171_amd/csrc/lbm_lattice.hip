@@ -92,7 +92,7 @@ __device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned total) {
 // z plane, tw in {64, 128, 256}; a wave is a 64-cell row segment. Wide tiles
 // keep the cache lines that odd-step shifted accesses split between
 // neighbouring row segments inside one workgroup.
-template <typename T, int PAR, int CL, bool BCG, bool FRC>
+template <typename T, int PAR, int CL, bool BCG, bool FRC, bool GR>
 __global__ __launch_bounds__(256) void k_stream_collide(Geo g, Physics ph, unsigned gx, unsigned gy, unsigned total,
                                                         unsigned tw_log2) {
     const unsigned tile = xcd_tile(blockIdx.x, total);
@@ -143,7 +143,8 @@ __global__ __launch_bounds__(256) void k_stream_collide(Geo g, Physics ph, unsig
         om1 = omega1_of<CL>(m, ph);
     }
     float o[27];
-    collide_unit_rates(m, om1, ph.omega2, Fx, Fy, Fz, o);
+    if (GR) collide_general(d, m, om1, ph.omega2, ph.omega_hi, Fx, Fy, Fz, o);
+    else collide_unit_rates(m, om1, ph.omega2, Fx, Fy, Fz, o);
     if (CL == CL_MLP && !valid) return;
 
     if (PAR == 0) {
@@ -165,44 +166,48 @@ __global__ __launch_bounds__(256) void k_stream_collide(Geo g, Physics ph, unsig
 
 // ------------------------------------------------------------ dispatch
 template <typename T, int PAR, int CL>
-static void launch_sc(bool bcg, bool frc, const Geo &g, const Physics &ph, hipStream_t s) {
+static void launch_sc(bool bcg, bool frc, bool gr, const Geo &g, const Physics &ph, hipStream_t s) {
     const unsigned twl = g.nx >= 256 ? 8u : (g.nx >= 128 ? 7u : 6u);
     const unsigned tw = 1u << twl, th = 256u >> twl;
     const unsigned gx = (g.nx + tw - 1) / tw, gy = (g.ny + th - 1) / th, total = gx * gy * (unsigned)g.nz;
     dim3 blk(256, 1, 1), grd(total, 1, 1);
-    if (bcg) {
-        if (frc) k_stream_collide<T, PAR, CL, true, true><<<grd, blk, 0, s>>>(g, ph, gx, gy, total, twl);
-        else k_stream_collide<T, PAR, CL, true, false><<<grd, blk, 0, s>>>(g, ph, gx, gy, total, twl);
+    // general rates only on the general-boundary path (periodic boxes included)
+    if (gr) {
+        if (frc) k_stream_collide<T, PAR, CL, true, true, true><<<grd, blk, 0, s>>>(g, ph, gx, gy, total, twl);
+        else k_stream_collide<T, PAR, CL, true, false, true><<<grd, blk, 0, s>>>(g, ph, gx, gy, total, twl);
+    } else if (bcg) {
+        if (frc) k_stream_collide<T, PAR, CL, true, true, false><<<grd, blk, 0, s>>>(g, ph, gx, gy, total, twl);
+        else k_stream_collide<T, PAR, CL, true, false, false><<<grd, blk, 0, s>>>(g, ph, gx, gy, total, twl);
     } else {
-        if (frc) k_stream_collide<T, PAR, CL, false, true><<<grd, blk, 0, s>>>(g, ph, gx, gy, total, twl);
-        else k_stream_collide<T, PAR, CL, false, false><<<grd, blk, 0, s>>>(g, ph, gx, gy, total, twl);
+        if (frc) k_stream_collide<T, PAR, CL, false, true, false><<<grd, blk, 0, s>>>(g, ph, gx, gy, total, twl);
+        else k_stream_collide<T, PAR, CL, false, false, false><<<grd, blk, 0, s>>>(g, ph, gx, gy, total, twl);
     }
 }
 
 template <typename T, int PAR>
-static int launch_sc_cl(int closure, bool bcg, bool frc, const Geo &g, const Physics &ph, hipStream_t s) {
+static int launch_sc_cl(int closure, bool bcg, bool frc, bool gr, const Geo &g, const Physics &ph, hipStream_t s) {
     switch (closure) {
-        case CL_NONE: launch_sc<T, PAR, CL_NONE>(bcg, frc, g, ph, s); return 0;
-        case CL_SMAG: launch_sc<T, PAR, CL_SMAG>(bcg, frc, g, ph, s); return 0;
-        case CL_MLP: launch_sc<T, PAR, CL_MLP>(bcg, frc, g, ph, s); return 0;
+        case CL_NONE: launch_sc<T, PAR, CL_NONE>(bcg, frc, gr, g, ph, s); return 0;
+        case CL_SMAG: launch_sc<T, PAR, CL_SMAG>(bcg, frc, gr, g, ph, s); return 0;
+        case CL_MLP: launch_sc<T, PAR, CL_MLP>(bcg, frc, gr, g, ph, s); return 0;
         default: return -1;
     }
 }
 
 template <typename T>
-static int launch_sc_par(int parity, int closure, bool bcg, bool frc, const Geo &g, const Physics &ph,
+static int launch_sc_par(int parity, int closure, bool bcg, bool frc, bool gr, const Geo &g, const Physics &ph,
                          hipStream_t s) {
-    return parity == 0 ? launch_sc_cl<T, 0>(closure, bcg, frc, g, ph, s)
-                       : launch_sc_cl<T, 1>(closure, bcg, frc, g, ph, s);
+    return parity == 0 ? launch_sc_cl<T, 0>(closure, bcg, frc, gr, g, ph, s)
+                       : launch_sc_cl<T, 1>(closure, bcg, frc, gr, g, ph, s);
 }
 
-int launch_stream_collide(int storage, int parity, int closure, bool general_bc, bool force, const Geo &g,
-                          const Physics &ph, hipStream_t s) {
+int launch_stream_collide(int storage, int parity, int closure, bool general_bc, bool force, bool general_rates,
+                          const Geo &g, const Physics &ph, hipStream_t s) {
     int rc;
     switch (storage) {
-        case 0: rc = launch_sc_par<float>(parity, closure, general_bc, force, g, ph, s); break;
-        case 1: rc = launch_sc_par<__half>(parity, closure, general_bc, force, g, ph, s); break;
-        case 2: rc = launch_sc_par<bf16_t>(parity, closure, general_bc, force, g, ph, s); break;
+        case 0: rc = launch_sc_par<float>(parity, closure, general_bc, force, general_rates, g, ph, s); break;
+        case 1: rc = launch_sc_par<__half>(parity, closure, general_bc, force, general_rates, g, ph, s); break;
+        case 2: rc = launch_sc_par<bf16_t>(parity, closure, general_bc, force, general_rates, g, ph, s); break;
         default: return -1;
     }
     if (rc) return rc;
