@@ -14,6 +14,12 @@ HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # keep the compiler from emitting packed FP32 arithmetic
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # x + 0 folds to x (force-free and boundary-free variants); the sign of a
+    # zero carries no meaning anywhere in the library
+    "-fno-signed-zeros",
+    # matrix-core accumulators in ordinary VGPRs: the closure reads them with
+    # vector instructions, AGPRs would cost a copy per element
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
 ]
 

@@ -33,12 +33,15 @@ template <> struct Store<__half> {
     static __device__ __forceinline__ float ld(const __half *p) { return __half2float(*p); }
     static __device__ __forceinline__ void st(__half *p, float v) { *p = __float2half_rn(v); }
 };
-// bfloat16: upper half of the float32 pattern, rounded to nearest even
-__device__ __forceinline__ uint16_t f32_to_bf16_bits(float v) {
-    uint32_t b = __float_as_uint(v);
-    if ((b & 0x7f800000u) == 0x7f800000u) return (uint16_t)(b >> 16) | ((b & 0xffffu) ? 0x40u : 0u);
-    b += 0x7fffu + ((b >> 16) & 1u);
-    return (uint16_t)(b >> 16);
+// bfloat16: upper half of the float32 pattern, rounded to nearest even by
+// the gfx950 conversion instruction (v_cvt_pk_bf16_f32, default round mode)
+typedef __bf16 bf16x2_native __attribute__((ext_vector_type(2)));
+typedef float f32x2_native __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint16_t f32_to_bf16_bits(float v) { return __builtin_bit_cast(uint16_t, (__bf16)v); }
+// two values in one instruction: lo in bits 0..15, hi in bits 16..31
+__device__ __forceinline__ uint32_t f32x2_to_bf16x2_bits(float lo, float hi) {
+    const f32x2_native v = {lo, hi};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2_native));
 }
 __device__ __forceinline__ float bf16_bits_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 template <> struct Store<bf16_t> {
@@ -59,6 +62,13 @@ struct CellMoments {
 // Density deviation, momentum and second raw moments of the deviations,
 // taken one axis at a time (z lines, then y, then x), then the velocity
 // u = (j + F/2)/rho and the normalised second central moments about u.
+// Hardware reciprocal and square root (v_rcp_f32, v_sqrt_f32: about 1 ulp),
+// used where a correctly rounded result buys nothing.
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+
+// FRC = false drops the force terms at compile time (F = 0).
+template <bool FRC = true>
 __device__ __forceinline__ CellMoments moments_of(const float d[27], float Fx, float Fy, float Fz) {
     float Z0[9], Z1[9], Z2[9];
 #pragma unroll
@@ -93,19 +103,31 @@ __device__ __forceinline__ CellMoments moments_of(const float d[27], float Fx, f
     CellMoments m;
     m.drho = m000;
     m.rho = 1.0f + m000;
-    const float irho = 1.0f / m.rho;
-    m.ux = (m100 + 0.5f * Fx) * irho;
-    m.uy = (m010 + 0.5f * Fy) * irho;
-    m.uz = (m001 + 0.5f * Fz) * irho;
+    const float irho = frcp(m.rho);
     // kappa_ab = Pi_ab - rho u_a u_b + (u_a F_b + u_b F_a)/2, Pi_aa = m_aa + 1/3
     // e_a = kappa_aa/rho - 1/3 = (m_aa - drho/3 - rho u_a^2 + u_a F_a) / rho
     const float d3 = m000 * (1.0f / 3.0f);
-    m.ex = (m200 - d3 - m.rho * m.ux * m.ux + m.ux * Fx) * irho;
-    m.ey = (m020 - d3 - m.rho * m.uy * m.uy + m.uy * Fy) * irho;
-    m.ez = (m002 - d3 - m.rho * m.uz * m.uz + m.uz * Fz) * irho;
-    m.kxy = (m110 - m.rho * m.ux * m.uy + 0.5f * (m.ux * Fy + m.uy * Fx)) * irho;
-    m.kxz = (m101 - m.rho * m.ux * m.uz + 0.5f * (m.ux * Fz + m.uz * Fx)) * irho;
-    m.kyz = (m011 - m.rho * m.uy * m.uz + 0.5f * (m.uy * Fz + m.uz * Fy)) * irho;
+    if (FRC) {
+        m.ux = (m100 + 0.5f * Fx) * irho;
+        m.uy = (m010 + 0.5f * Fy) * irho;
+        m.uz = (m001 + 0.5f * Fz) * irho;
+        m.ex = (m200 - d3 - m.rho * m.ux * m.ux + m.ux * Fx) * irho;
+        m.ey = (m020 - d3 - m.rho * m.uy * m.uy + m.uy * Fy) * irho;
+        m.ez = (m002 - d3 - m.rho * m.uz * m.uz + m.uz * Fz) * irho;
+        m.kxy = (m110 - m.rho * m.ux * m.uy + 0.5f * (m.ux * Fy + m.uy * Fx)) * irho;
+        m.kxz = (m101 - m.rho * m.ux * m.uz + 0.5f * (m.ux * Fz + m.uz * Fx)) * irho;
+        m.kyz = (m011 - m.rho * m.uy * m.uz + 0.5f * (m.uy * Fz + m.uz * Fy)) * irho;
+    } else {
+        m.ux = m100 * irho;
+        m.uy = m010 * irho;
+        m.uz = m001 * irho;
+        m.ex = (m200 - d3 - m.rho * m.ux * m.ux) * irho;
+        m.ey = (m020 - d3 - m.rho * m.uy * m.uy) * irho;
+        m.ez = (m002 - d3 - m.rho * m.uz * m.uz) * irho;
+        m.kxy = (m110 - m.rho * m.ux * m.uy) * irho;
+        m.kxz = (m101 - m.rho * m.ux * m.uz) * irho;
+        m.kyz = (m011 - m.rho * m.uy * m.uz) * irho;
+    }
     return m;
 }
 
@@ -113,14 +135,14 @@ __device__ __forceinline__ CellMoments moments_of(const float d[27], float Fx, f
 __device__ __forceinline__ float q_norm(const CellMoments &m) {
     const float tr3 = (m.ex + m.ey + m.ez) * (1.0f / 3.0f);
     const float a = m.ex - tr3, b = m.ey - tr3, c = m.ez - tr3;
-    return sqrtf(a * a + b * b + c * c + 2.0f * (m.kxy * m.kxy + m.kxz * m.kxz + m.kyz * m.kyz));
+    return fsqrt(a * a + b * b + c * c + 2.0f * (m.kxy * m.kxy + m.kxz * m.kxz + m.kyz * m.kyz));
 }
 
 // Smagorinsky shear rate in the closed form of Hou et al. (1996):
 // tau = (tau0 + sqrt(tau0^2 + 18 sqrt(2) Cs^2 Q)) / 2.
 __device__ __forceinline__ float smag_omega(float Q, float tau0, float cs2_18sqrt2) {
-    const float tau = 0.5f * (tau0 + sqrtf(tau0 * tau0 + cs2_18sqrt2 * Q));
-    return 1.0f / tau;
+    const float tau = 0.5f * (tau0 + fsqrt(tau0 * tau0 + cs2_18sqrt2 * Q));
+    return frcp(tau);
 }
 
 // One 1-D inverse pass on a triple of central moments (k0,k1,k2) about u:

@@ -24,7 +24,10 @@ struct MlpDev {
     uint16_t W1[32 * 8];    // [out][in], inputs padded 6 -> 8 with zeros
     uint16_t W2[32 * 32];   // [out][in]
     uint16_t W2T[32 * 32];  // [in][out] (backward pass)
-    float b1[32], b2[32], w3[32], b3;
+    alignas(16) float b1[32];  // 16-byte aligned: read as float4 by the kernels
+    alignas(16) float b2[32];
+    alignas(16) float w3[32];
+    float b3;
     float mu[8], inv_sigma[8];
     float nu_scale;
 };

@@ -92,53 +92,76 @@ __device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned total) {
 // z plane, tw in {64, 128, 256}; a wave is a 64-cell row segment. Wide tiles
 // keep the cache lines that odd-step shifted accesses split between
 // neighbouring row segments inside one workgroup.
+// A copy of g whose plane stride the compiler cannot see through (an empty
+// asm that claims to rewrite the scalar register pair), so that addresses
+// built from it are recomputed rather than kept live.
+__device__ __forceinline__ Geo with_opaque_stride(const Geo &g) {
+    Geo r = g;
+    size_t P = r.P;
+    asm volatile("" : "+s"(P));
+    r.P = P;
+    return r;
+}
+
+__device__ __forceinline__ void opaque_v(uint32_t &v) { asm volatile("" : "+v"(v)); }
+
+// Element offsets of the periodic neighbours of (x, y, z): xs[dx + 1] and
+// rows[(dy + 1) + 3 (dz + 1)] for dx, dy, dz in {-1, 0, 1}.
+__device__ __forceinline__ void periodic_offsets(const Geo &g, int x, int y, int z, uint32_t xs[3], uint32_t rows[9]) {
+    xs[0] = x == 0 ? g.nx - 1 : x - 1;
+    xs[1] = x;
+    xs[2] = x == g.nx - 1 ? 0 : x + 1;
+    // row starts y nx and plane starts z nx ny of the wrapped neighbours:
+    // two multiplies, the rest adds and selects
+    const uint32_t nx = (uint32_t)g.nx, plane = nx * (uint32_t)g.ny;
+    const uint32_t yr = (uint32_t)y * nx, zp = (uint32_t)z * plane;
+    const uint32_t ys[3] = {y == 0 ? plane - nx : yr - nx, yr, y == g.ny - 1 ? 0u : yr + nx};
+    const uint32_t zs[3] = {z == 0 ? (uint32_t)(g.nz - 1) * plane : zp - plane, zp, z == g.nz - 1 ? 0u : zp + plane};
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) rows[a + 3 * b] = zs[b] + ys[a];
+}
+
 template <typename T, int PAR, int CL, bool BCG, bool FRC, bool GR>
 __global__ __launch_bounds__(256) void k_stream_collide(Geo g, Physics ph, unsigned gx, unsigned gy, unsigned total,
                                                         unsigned tw_log2) {
     const unsigned tile = xcd_tile(blockIdx.x, total);
     const unsigned tw = 1u << tw_log2, th = 256u >> tw_log2;
-    const int x = (int)((tile % gx) * tw + (threadIdx.x & (tw - 1)));
-    const int y = (int)(((tile / gx) % gy) * th + (threadIdx.x >> tw_log2));
+    const int x0 = (int)((tile % gx) * tw + (threadIdx.x & (tw - 1)));
+    const int y0 = (int)(((tile / gx) % gy) * th + (threadIdx.x >> tw_log2));
     const int z = (int)(tile / (gx * gy));
     // the learned closure runs on the matrix cores, which need every lane of
-    // the wave: out-of-range lanes then compute on a rest state and store nothing
-    const bool valid = x < g.nx && y < g.ny;
+    // the wave: out-of-range lanes then recompute the nearest edge cell of the
+    // row / column and store nothing
+    const bool valid = x0 < g.nx && y0 < g.ny;
     if (CL != CL_MLP && !valid) return;
+    const int x = CL == CL_MLP ? min(x0, g.nx - 1) : x0;
+    const int y = CL == CL_MLP ? min(y0, g.ny - 1) : y0;
     const size_t cell = cidx(g, x, y, z);
     // fast path (no boundary rules): 32-bit offsets, see Unroll32
     const uint32_t cell32 = (uint32_t)cell;
     float d[27];
     uint32_t xs[3], rows[9];
-    if (CL == CL_MLP && !valid) {
-#pragma unroll
-        for (int i = 0; i < 27; ++i) d[i] = 0.0f;
-    } else if (PAR == 0) {
+    if (PAR == 0) {
         if (BCG) Unroll<T, 0>::read_natural(g, cell, d);
         else Unroll32<T, 0>::read_natural(g, cell32 * (uint32_t)sizeof(T), d);
     } else if (!BCG) {
-        xs[0] = x == 0 ? g.nx - 1 : x - 1;
-        xs[1] = x;
-        xs[2] = x == g.nx - 1 ? 0 : x + 1;
-        const uint32_t ys[3] = {(uint32_t)(y == 0 ? g.ny - 1 : y - 1), (uint32_t)y, (uint32_t)(y == g.ny - 1 ? 0 : y + 1)};
-        const uint32_t zs[3] = {(uint32_t)(z == 0 ? g.nz - 1 : z - 1), (uint32_t)z, (uint32_t)(z == g.nz - 1 ? 0 : z + 1)};
-#pragma unroll
-        for (int b = 0; b < 3; ++b)
-#pragma unroll
-            for (int a = 0; a < 3; ++a) rows[a + 3 * b] = (zs[b] * (uint32_t)g.ny + ys[a]) * (uint32_t)g.nx;
+        periodic_offsets(g, x, y, z, xs, rows);
         Unroll32<T, 0>::read_periodic(g, xs, rows, d);
     } else {
         Unroll<T, 0>::read_sw(g, x, y, z, d);
     }
 
     float Fx = 0.f, Fy = 0.f, Fz = 0.f;
-    if (FRC && valid) cell_force(ph, (size_t)g.nx * g.ny * g.nz, cell, x, y, z, Fx, Fy, Fz);
-    const CellMoments m = moments_of(d, Fx, Fy, Fz);
+    if (FRC) cell_force(ph, (size_t)g.nx * g.ny * g.nz, cell, x, y, z, Fx, Fy, Fz);
+    const CellMoments m = moments_of<FRC>(d, Fx, Fy, Fz);
     float om1;
     if (CL == CL_MLP) {
         float f[6];
         closure_features(m, ph.tau0, f);
         const float nut = mlp_nu_t_wave(*ph.mlp, f);
-        om1 = 1.0f / (3.0f * (ph.nu0 + nut) + 0.5f);
+        om1 = frcp(3.0f * (ph.nu0 + nut) + 0.5f);
     } else {
         om1 = omega1_of<CL>(m, ph);
     }
@@ -146,10 +169,30 @@ __global__ __launch_bounds__(256) void k_stream_collide(Geo g, Physics ph, unsig
     if (GR) collide_general(d, m, om1, ph.omega2, ph.omega_hi, Fx, Fy, Fz, o);
     else collide_unit_rates(m, om1, ph.omega2, Fx, Fy, Fz, o);
     if (CL == CL_MLP && !valid) return;
+    // the closure variant needs scalar registers for the network: an opaque
+    // copy of the plane stride makes the compiler rebuild the plane bases of
+    // the stores here instead of holding them from the loads on
+    // (and the 32-bit offsets are re-declared in this block, where the store
+    // instructions can then take them as 32-bit vector offsets)
+    const Geo gw = CL == CL_MLP ? with_opaque_stride(g) : g;
+    // (the odd step rebuilds its neighbour offsets from x, y, z rather than
+    // holding twelve registers through the network)
+    uint32_t boff = cell32 * (uint32_t)sizeof(T);
+    if (CL == CL_MLP && !BCG) {
+        if (PAR == 0) {
+            opaque_v(boff);
+        } else {
+            uint32_t xo = (uint32_t)x, yo = (uint32_t)y, zo = (uint32_t)z;
+            opaque_v(xo);
+            opaque_v(yo);
+            opaque_v(zo);
+            periodic_offsets(g, (int)xo, (int)yo, (int)zo, xs, rows);
+        }
+    }
 
     if (PAR == 0) {
         if (BCG) Unroll<T, 0>::write_swap_local(g, cell, o);
-        else Unroll32<T, 0>::write_swap_local(g, cell32 * (uint32_t)sizeof(T), o);
+        else Unroll32<T, 0>::write_swap_local(gw, boff, o);
         if (BCG && g.bc_x == BC_INOUT && x == g.nx - 1) {
             T *G = (T *)g.ghost;
 #pragma unroll
@@ -157,7 +200,7 @@ __global__ __launch_bounds__(256) void k_stream_collide(Geo g, Physics ph, unsig
                 Store<T>::st(G + (size_t)(J / 3) * g.ny * g.nz + y + (size_t)g.ny * z, o[J]);
         }
     } else if (!BCG) {
-        Unroll32<T, 0>::write_periodic(g, xs, rows, o);
+        Unroll32<T, 0>::write_periodic(gw, xs, rows, o);
     } else {
         Unroll<T, 0>::write_push(g, x, y, z, o);
         if (g.bc_x == BC_INOUT) odd_boundary_extras<T>(g, x, y, z, o);

@@ -36,67 +36,133 @@ __device__ __forceinline__ void closure_features(const CellMoments &m, float tau
     const float q = q_norm(m);
     f[3] = q;
     f[4] = m.drho;
-    const float tau = 0.5f * (tau0 + sqrtf(tau0 * tau0 + 18.0f * 1.41421356237f * 0.01f * q));
+    const float tau = 0.5f * (tau0 + fsqrt(tau0 * tau0 + 18.0f * 1.41421356237f * 0.01f * q));
     f[5] = (tau - tau0) * (1.0f / 3.0f);
 }
 
-__device__ __forceinline__ float softplusf(float z) { return fmaxf(z, 0.0f) + log1pf(expf(-fabsf(z))); }
+// max(x, 0) as one integer max on the bit pattern: a negative float has a
+// negative two's-complement pattern, a positive one keeps its order
+__device__ __forceinline__ float relu(float x) { return __int_as_float(max(__float_as_int(x), 0)); }
+
+// softplus(z) = max(z, 0) + log(1 + e), e = exp(-|z|) in (0, 1]. The
+// logarithm uses log(1 + e) = 2 atanh(s), s = e / (2 + e) in (0, 1/3], and
+// the odd series 2 (s + s^3/3 + ... + s^15/15): the first dropped term is
+// below s^16/17 < 2e-9 of the sum, and the result keeps its relative
+// accuracy for tiny e, where log(1 + e) would round to zero.
+__device__ __forceinline__ float softplusf(float z) {
+    const float e = expf(-fabsf(z));
+    const float s = e * frcp(2.0f + e), t = s * s;
+    float p = 1.0f / 15.0f;
+    p = fmaf(p, t, 1.0f / 13.0f);
+    p = fmaf(p, t, 1.0f / 11.0f);
+    p = fmaf(p, t, 1.0f / 9.0f);
+    p = fmaf(p, t, 1.0f / 7.0f);
+    p = fmaf(p, t, 1.0f / 5.0f);
+    p = fmaf(p, t, 1.0f / 3.0f);
+    p = fmaf(p, t, 1.0f);
+    return fmaxf(z, 0.0f) + 2.0f * s * p;
+}
 
 // Normalised, bf16-rounded features of the lane's cell packed as 4 x 2 bf16.
 __device__ __forceinline__ void pack_features(const MlpDev &M, const float f[6], uint32_t p[4]) {
-    short s[8];
+    float s[6];
 #pragma unroll
-    for (int j = 0; j < 6; ++j) {
-        const float d = f[j] - M.mu[j];
-        s[j] = bf16s(d * M.inv_sigma[j]);
-    }
-    s[6] = 0;
-    s[7] = 0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) p[q] = (uint32_t)(uint16_t)s[2 * q] | ((uint32_t)(uint16_t)s[2 * q + 1] << 16);
+    for (int j = 0; j < 6; ++j) s[j] = (f[j] - M.mu[j]) * M.inv_sigma[j];
+    p[0] = f32x2_to_bf16x2_bits(s[0], s[1]);
+    p[1] = f32x2_to_bf16x2_bits(s[2], s[3]);
+    p[2] = f32x2_to_bf16x2_bits(s[4], s[5]);
+    p[3] = 0u;
 }
 
+typedef uint32_t u32x2_t __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ bf16x4_t as_bf16x4(uint32_t lo, uint32_t hi) {
-    bf16x4_t v;
-    v[0] = (short)(lo & 0xffff);
-    v[1] = (short)(lo >> 16);
-    v[2] = (short)(hi & 0xffff);
-    v[3] = (short)(hi >> 16);
-    return v;
+    const u32x2_t v = {lo, hi};
+    return __builtin_bit_cast(bf16x4_t, v);
 }
 
-// Per-half-wave network evaluation. xin: B operand of layer 1 for this half.
-// Returns z for the cell in column lane % 32 (valid in both lane halves).
-__device__ __forceinline__ float mlp_half(const MlpDev &M, bf16x4_t xin, int lane) {
-    const int row = lane & 31, hi = lane >> 5;
-    // layer 1
-    f32x16_t acc;
+// The network operands one lane needs, loaded once per wave and shared by
+// both half-wave evaluations: its row of W1 and W2 (A operands) and the 16
+// bias / output-weight entries of the D-register rows it holds.
+struct MlpLane {
+    bf16x4_t w1, w2[4];
+    f32x16_t b1, b2, w3;
+};
+
+__device__ __forceinline__ f32x16_t load_drows(const float *v, int hi) {
+    f32x16_t r;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) acc[r] = M.b1[8 * (r >> 2) + 4 * hi + (r & 3)];
-    {
-        const uint2 w = *(const uint2 *)(M.W1 + row * 8 + 4 * hi);
-        acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(as_bf16x4(w.x, w.y), xin, acc, 0, 0, 0);
+    for (int q = 0; q < 4; ++q) {
+        const float4 t = *(const float4 *)(v + 8 * q + 4 * hi);
+        r[4 * q] = t.x;
+        r[4 * q + 1] = t.y;
+        r[4 * q + 2] = t.z;
+        r[4 * q + 3] = t.w;
     }
-    // relu + bf16: registers 4s..4s+3 form the B operand of K-block s
-    bf16x4_t h[4];
-#pragma unroll
-    for (int s = 0; s < 4; ++s)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) h[s][j] = bf16s(fmaxf(acc[4 * s + j], 0.0f));
-    // layer 2
-#pragma unroll
-    for (int r = 0; r < 16; ++r) acc[r] = M.b2[8 * (r >> 2) + 4 * hi + (r & 3)];
+    return r;
+}
+
+__device__ __forceinline__ MlpLane mlp_lane(const MlpDev &M, int lane) {
+    const int row = lane & 31, hi = lane >> 5;
+    MlpLane L;
+    const uint2 w = *(const uint2 *)(M.W1 + row * 8 + 4 * hi);
+    L.w1 = as_bf16x4(w.x, w.y);
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-        const uint2 w = *(const uint2 *)(M.W2 + row * 32 + 8 * s + 4 * hi);
-        acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(as_bf16x4(w.x, w.y), h[s], acc, 0, 0, 0);
+        const uint2 v = *(const uint2 *)(M.W2 + row * 32 + 8 * s + 4 * hi);
+        L.w2[s] = as_bf16x4(v.x, v.y);
+    }
+    L.b1 = load_drows(M.b1, hi);
+    L.b2 = load_drows(M.b2, hi);
+    L.w3 = load_drows(M.w3, hi);
+    return L;
+}
+
+typedef short s16x2_t __attribute__((ext_vector_type(2)));
+// ReLU of two packed bfloat16 values as one packed 16-bit integer max: the
+// sign bit of a bfloat16 is the sign bit of its 16-bit pattern, and rounding
+// to bfloat16 keeps the sign, so relu(bf16(x)) = bf16(relu(x)).
+__device__ __forceinline__ uint32_t relu_bf16x2(uint32_t v) {
+    const s16x2_t z = {0, 0};
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(s16x2_t, v), z));
+}
+
+// relu(H1) in bfloat16 from the layer-1 accumulator: registers 4s..4s+3
+// form the B operand of K-block s of layer 2
+__device__ __forceinline__ void hidden_bf16(const f32x16_t &acc, bf16x4_t h[4]) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+        h[s] = as_bf16x4(relu_bf16x2(f32x2_to_bf16x2_bits(acc[4 * s], acc[4 * s + 1])),
+                         relu_bf16x2(f32x2_to_bf16x2_bits(acc[4 * s + 2], acc[4 * s + 3])));
+}
+
+// Both half-wave evaluations, interleaved so that the dependent matrix-core
+// chains of one half overlap the other's. x0 / x1: B operands of layer 1 for
+// the cells of half 0 / 1. Returns z - b3 for the cell in column lane % 32
+// of each half (valid in both lane halves).
+__device__ __forceinline__ void mlp_halves(const MlpLane &L, bf16x4_t x0, bf16x4_t x1, float &z0, float &z1) {
+    // layer 1 (bias as the accumulator input)
+    f32x16_t a0 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(L.w1, x0, L.b1, 0, 0, 0);
+    f32x16_t a1 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(L.w1, x1, L.b1, 0, 0, 0);
+    bf16x4_t h0[4], h1[4];
+    hidden_bf16(a0, h0);
+    hidden_bf16(a1, h1);
+    // layer 2
+    a0 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(L.w2[0], h0[0], L.b2, 0, 0, 0);
+    a1 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(L.w2[0], h1[0], L.b2, 0, 0, 0);
+#pragma unroll
+    for (int s = 1; s < 4; ++s) {
+        a0 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(L.w2[s], h0[s], a0, 0, 0, 0);
+        a1 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(L.w2[s], h1[s], a1, 0, 0, 0);
     }
     // layer 3: this lane holds 16 of the 32 hidden units of its column
-    float z = 0.0f;
+    float s0 = 0.0f, s1 = 0.0f;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) z = fmaf(M.w3[8 * (r >> 2) + 4 * hi + (r & 3)], fmaxf(acc[r], 0.0f), z);
-    z += __shfl_xor(z, 32);
-    return z + M.b3;
+    for (int r = 0; r < 16; ++r) {
+        s0 = fmaf(L.w3[r], relu(a0[r]), s0);
+        s1 = fmaf(L.w3[r], relu(a1[r]), s1);
+    }
+    z0 = s0 + __shfl_xor(s0, 32);
+    z1 = s1 + __shfl_xor(s1, 32);
 }
 
 // Eddy viscosity of the lane's own cell; all 64 lanes of the wave must call
@@ -114,9 +180,10 @@ __device__ __forceinline__ float mlp_nu_t_wave(const MlpDev &M, const float f[6]
     const uint32_t r1 = (uint32_t)__shfl_xor((int)s1, 32);
     const bf16x4_t x0 = lane < 32 ? as_bf16x4(p[0], p[1]) : as_bf16x4(r0, r1);
     const bf16x4_t x1 = lane < 32 ? as_bf16x4(r0, r1) : as_bf16x4(p[2], p[3]);
-    const float z0 = mlp_half(M, x0, lane);
-    const float z1 = mlp_half(M, x1, lane);
-    const float z = lane < 32 ? z0 : z1;
+    const MlpLane L = mlp_lane(M, lane);
+    float z0, z1;
+    mlp_halves(L, x0, x1, z0, z1);
+    const float z = (lane < 32 ? z0 : z1) + M.b3;
     return M.nu_scale * softplusf(z);
 }
 
