@@ -136,6 +136,9 @@ __global__ __launch_bounds__(256) void k_stream_collide(Geo g, Physics ph, unsig
     // row / column and store nothing
     const bool valid = x0 < g.nx && y0 < g.ny;
     if (CL != CL_MLP && !valid) return;
+    // network operands: DMA into LDS now, in flight with the population loads
+    __shared__ MlpLds mlp_lds;
+    if (CL == CL_MLP) mlp_stage_lds(ph.mlp, &mlp_lds);
     const int x = CL == CL_MLP ? min(x0, g.nx - 1) : x0;
     const int y = CL == CL_MLP ? min(y0, g.ny - 1) : y0;
     const size_t cell = cidx(g, x, y, z);
@@ -160,7 +163,8 @@ __global__ __launch_bounds__(256) void k_stream_collide(Geo g, Physics ph, unsig
     if (CL == CL_MLP) {
         float f[6];
         closure_features(m, ph.tau0, f);
-        const float nut = mlp_nu_t_wave(*ph.mlp, f);
+        mlp_stage_wait();
+        const float nut = mlp_nu_t_wave(*ph.mlp, mlp_lds, f);
         om1 = frcp(3.0f * (ph.nu0 + nut) + 0.5f);
     } else {
         om1 = omega1_of<CL>(m, ph);

@@ -63,12 +63,15 @@ void mlp_pack(const float *blob, MlpDev *M) {
 constexpr int TB = 256;
 
 __global__ __launch_bounds__(TB) void k_mlp_forward(const MlpDev *M, const float *feat, size_t m, float *nu) {
+    __shared__ MlpLds S;
+    mlp_stage_lds(M, &S);
     const size_t q = blockIdx.x * (size_t)TB + threadIdx.x;
     const bool valid = q < m;
     float f[6];
 #pragma unroll
     for (int j = 0; j < 6; ++j) f[j] = valid ? feat[q * 6 + j] : M->mu[j];
-    const float v = mlp_nu_t_wave(*M, f);
+    mlp_stage_wait();
+    const float v = mlp_nu_t_wave(*M, S, f);
     if (valid) nu[q] = v;
 }
 

@@ -14,6 +14,7 @@
 // s of layer 2: the hidden layer never leaves registers. Feature vectors of
 // one cell per lane reach the B layout of layer 1 with one cross-half swap.
 #pragma once
+#include <cstddef>
 #include "lbm_device.h"
 #include "lbm_internal.h"
 
@@ -80,8 +81,48 @@ __device__ __forceinline__ bf16x4_t as_bf16x4(uint32_t lo, uint32_t hi) {
     return __builtin_bit_cast(bf16x4_t, v);
 }
 
-// The network operands one lane needs, loaded once per wave and shared by
-// both half-wave evaluations: its row of W1 and W2 (A operands) and the 16
+// Copy of the network operands in LDS, one per workgroup: W1 and W2 (the A
+// operands) and b1, b2, w3. Every lane of a half-wave reads the same bias and
+// output-weight entries, so LDS broadcasts them; read from global memory they
+// would cost each wave 17 vector loads of up to 1 KB behind its population
+// loads.
+struct MlpLds {
+    uint16_t W1[32 * 8];
+    uint16_t W2[32 * 32];
+    float b1[32], b2[32], w3[32];
+};
+static_assert(sizeof(MlpLds) == 2944, "LDS image of the network");
+static_assert(offsetof(MlpDev, W2) == offsetof(MlpDev, W1) + sizeof(MlpLds::W1), "W1, W2 adjacent");
+static_assert(offsetof(MlpDev, b2) == offsetof(MlpDev, b1) + 128 && offsetof(MlpDev, w3) == offsetof(MlpDev, b1) + 256,
+              "b1, b2, w3 adjacent");
+static_assert(offsetof(MlpDev, b1) % 16 == 0, "16-byte chunks");
+
+// Start the copy of the network into LDS: 184 chunks of 16 bytes, one per
+// thread of the first 184 threads of the block (blockDim.x >= 192), moved by
+// the global-to-LDS DMA of gfx950 (global_load_lds_dwordx4) without passing
+// through registers. Lane l of a wave writes chunk (wave base + l).
+__device__ __forceinline__ void mlp_stage_lds(const MlpDev *M, MlpLds *S) {
+    constexpr unsigned NW12 = (sizeof(MlpLds::W1) + sizeof(MlpLds::W2)) / 16;  // 160
+    constexpr unsigned NCH = sizeof(MlpLds) / 16;                                  // 184
+    const unsigned c = threadIdx.x, wave_base = threadIdx.x & ~63u;
+    if (wave_base < NCH && c < NCH) {
+        const char *src = c < NW12 ? (const char *)M->W1 + 16 * c : (const char *)M->b1 + 16 * (c - NW12);
+        __builtin_amdgcn_global_load_lds((const void *)src,
+                                         (__attribute__((address_space(3))) void *)((char *)S + 16 * wave_base), 16, 0,
+                                         0);
+    }
+}
+
+// Wait for the copy: the DMA counts as an outstanding vector-memory load of
+// the issuing wave, then the block barrier makes every wave's part visible.
+// Every thread of the block must call this.
+__device__ __forceinline__ void mlp_stage_wait() {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+}
+
+// The network operands one lane needs, read once per wave from LDS and shared
+// by both half-wave evaluations: its row of W1 and W2 (A operands) and the 16
 // bias / output-weight entries of the D-register rows it holds.
 struct MlpLane {
     bf16x4_t w1, w2[4];
@@ -101,19 +142,19 @@ __device__ __forceinline__ f32x16_t load_drows(const float *v, int hi) {
     return r;
 }
 
-__device__ __forceinline__ MlpLane mlp_lane(const MlpDev &M, int lane) {
+__device__ __forceinline__ MlpLane mlp_lane(const MlpLds &S, int lane) {
     const int row = lane & 31, hi = lane >> 5;
     MlpLane L;
-    const uint2 w = *(const uint2 *)(M.W1 + row * 8 + 4 * hi);
+    const uint2 w = *(const uint2 *)(S.W1 + row * 8 + 4 * hi);
     L.w1 = as_bf16x4(w.x, w.y);
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-        const uint2 v = *(const uint2 *)(M.W2 + row * 32 + 8 * s + 4 * hi);
+        const uint2 v = *(const uint2 *)(S.W2 + row * 32 + 8 * s + 4 * hi);
         L.w2[s] = as_bf16x4(v.x, v.y);
     }
-    L.b1 = load_drows(M.b1, hi);
-    L.b2 = load_drows(M.b2, hi);
-    L.w3 = load_drows(M.w3, hi);
+    L.b1 = load_drows(S.b1, hi);
+    L.b2 = load_drows(S.b2, hi);
+    L.w3 = load_drows(S.w3, hi);
     return L;
 }
 
@@ -167,7 +208,8 @@ __device__ __forceinline__ void mlp_halves(const MlpLane &L, bf16x4_t x0, bf16x4
 
 // Eddy viscosity of the lane's own cell; all 64 lanes of the wave must call
 // this together (matrix-core instructions act on the whole wave).
-__device__ __forceinline__ float mlp_nu_t_wave(const MlpDev &M, const float f[6]) {
+// S: the LDS copy of the network (mlp_stage_lds, mlp_stage_wait).
+__device__ __forceinline__ float mlp_nu_t_wave(const MlpDev &M, const MlpLds &S, const float f[6]) {
     const int lane = (int)__lane_id();
     uint32_t p[4];
     pack_features(M, f, p);
@@ -180,7 +222,7 @@ __device__ __forceinline__ float mlp_nu_t_wave(const MlpDev &M, const float f[6]
     const uint32_t r1 = (uint32_t)__shfl_xor((int)s1, 32);
     const bf16x4_t x0 = lane < 32 ? as_bf16x4(p[0], p[1]) : as_bf16x4(r0, r1);
     const bf16x4_t x1 = lane < 32 ? as_bf16x4(r0, r1) : as_bf16x4(p[2], p[3]);
-    const MlpLane L = mlp_lane(M, lane);
+    const MlpLane L = mlp_lane(S, lane);
     float z0, z1;
     mlp_halves(L, x0, x1, z0, z1);
     const float z = (lane < 32 ? z0 : z1) + M.b3;
