@@ -66,7 +66,10 @@ class RotorDesc(C.Structure):
                 ("r", C.POINTER(C.c_double)), ("chord", C.POINTER(C.c_double)),
                 ("twist_deg", C.POINTER(C.c_double)), ("dl", C.POINTER(C.c_double)),
                 ("n_polar", C.c_int), ("alpha_deg", C.POINTER(C.c_double)),
-                ("cl", C.POINTER(C.c_double)), ("cd", C.POINTER(C.c_double))]
+                ("cl", C.POINTER(C.c_double)), ("cd", C.POINTER(C.c_double)),
+                ("kernel", C.c_int), ("tip_loss", C.c_int)]
+
+KERNEL_GAUSS, KERNEL_ROMA3 = 0, 1
 
 
 _D = C.POINTER(C.c_double)
@@ -111,6 +114,9 @@ def _declare(L):
                                   C.c_double, C.c_double, C.c_double, C.c_int,
                                   _D, _D, _D, _D, _D, _D]),
         "orc_spread_point": (v, [C.c_void_p, _D, _D, C.c_double, _D]),
+        "orc_spread_point_roma": (v, [C.c_void_p, _D, _D, _D]),
+        "orc_roma_phi": (C.c_double, [C.c_double]),
+        "orc_tip_loss": (C.c_double, [C.c_int, C.c_double, C.c_double, C.c_double]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -205,6 +211,17 @@ def blade_element(rho, wn, wt, chord, dl, twist_deg, pitch_deg, polar):
                             _p(a), _p(cl), _p(cd), C.byref(fn), C.byref(ft),
                             C.byref(al))
     return fn.value, ft.value, al.value
+
+
+def roma_phi(r):
+    """The 1-D factor of the Roma et al. 3-point discrete delta."""
+    return lib().orc_roma_phi(float(r))
+
+
+def tip_loss(n_blades, radius, r, phi_rad):
+    """Prandtl tip-loss factor (the oracle's reading of the paper's
+    Glauert-type correction)."""
+    return lib().orc_tip_loss(int(n_blades), float(radius), float(r), float(phi_rad))
 
 
 def inflow_plane(mean, box, advect, t):
@@ -323,6 +340,8 @@ class Grid:
         d.twist_deg, d.dl = _p(arrs["twist_deg"]), _p(arrs["dl"])
         d.n_polar = len(pol["alpha_deg"])
         d.alpha_deg, d.cl, d.cd = _p(pol["alpha_deg"]), _p(pol["cl"]), _p(pol["cd"])
+        d.kernel = {"gauss": KERNEL_GAUSS, "roma3": KERNEL_ROMA3}[rotor.get("kernel", "gauss")]
+        d.tip_loss = int(bool(rotor.get("tip_loss", False)))
         if lib().orc_set_rotor(self._h, rid, C.byref(d)) != 0:
             raise ValueError("oracle: bad rotor")
         self._rotor_np = getattr(self, "_rotor_np", {})
@@ -347,7 +366,10 @@ class Grid:
         lib().orc_trilinear(self._h, _p(field.reshape(-1)), ncomp, _p(_f64(x)), _p(out))
         return out
 
-    def spread_point(self, xp, Fp, eps):
+    def spread_point(self, xp, Fp, eps, kernel="gauss"):
         F = np.zeros((3,) + self.shape)
-        lib().orc_spread_point(self._h, _p(_f64(xp)), _p(_f64(Fp)), float(eps), _p(F))
+        if kernel == "roma3":
+            lib().orc_spread_point_roma(self._h, _p(_f64(xp)), _p(_f64(Fp)), _p(F))
+        else:
+            lib().orc_spread_point(self._h, _p(_f64(xp)), _p(_f64(Fp)), float(eps), _p(F))
         return F

@@ -95,7 +95,11 @@ typedef struct {
     const double *r, *chord, *twist_deg, *dl;  /* n_points each */
     int n_polar;
     const double *alpha_deg, *cl, *cd;          /* uniform alpha grid */
+    int kernel;    /* ORC_KERNEL_GAUSS or ORC_KERNEL_ROMA3 */
+    int tip_loss;  /* 1: blade-element force times the tip-loss factor */
 } orc_rotor_desc;
+#define ORC_KERNEL_GAUSS 0
+#define ORC_KERNEL_ROMA3 1
 
 int  orc_set_rotor(orc_grid *g, int id, const orc_rotor_desc *d);
 void orc_rotor_loads(const orc_grid *g, int id, double out[3], double *pt_force);
@@ -112,6 +116,10 @@ void orc_blade_element(double rho, const double urel_axial,
                        double *alpha_out);
 void orc_spread_point(const orc_grid *g, const double xp[3],
                       const double Fp[3], double eps, double *F);
+double orc_roma_phi(double r);
+void orc_spread_point_roma(const orc_grid *g, const double xp[3],
+                           const double Fp[3], double *F);
+double orc_tip_loss(int n_blades, double radius, double r, double phi_rad);
 
 /* internal: the ALM sub-steps of one time step, called by orc_step */
 void orc_alm_step(orc_grid *g);

@@ -18,7 +18,13 @@
  *   the regularisation kernel is the Gaussian
  *   exp(-|d|^2/eps^2) / (eps^3 pi^(3/2)) on the 13^3 nodes round(x_p) +- 6,
  *   renormalised to unit sum per node, so that the total force is conserved
- *   exactly (the property the paper values in its discrete kernel).
+ *   exactly (the property the paper values in its discrete kernel), or the
+ *   paper's own choice, the 3-point discrete delta of Roma, Peskin and Berger
+ *   (1999) as a product of 1-D factors in lattice units;
+ *   the optional "Glauert type" tip-loss correction (Sec. 2.2, Sec. 4) is
+ *   Prandtl's factor F = 2/pi arccos(exp(-B (R - r) / (2 r |sin phi|))),
+ *   phi the inflow angle between the relative wind and the rotor plane,
+ *   multiplying the whole blade-element force (lift and drag).
  */
 #include "orc.h"
 #include <math.h>
@@ -212,6 +218,62 @@ void orc_spread_point(const orc_grid *g, const double xp[3], const double Fp[3],
             }
 }
 
+/* Roma et al. 3-point discrete delta in one dimension (lattice units): the
+ * unique function with support |r| < 3/2 whose shifts sum to one, have zero
+ * first moment and sum of squares 1/2 at every r. */
+double orc_roma_phi(double r)
+{
+    double a = fabs(r);
+    if (a <= 0.5)
+        return (1.0 + sqrt(1.0 - 3.0 * a * a)) / 3.0;
+    if (a < 1.5) {
+        double b = 1.0 - a;
+        return (5.0 - 3.0 * a - sqrt(1.0 - 3.0 * b * b)) / 6.0;
+    }
+    return 0.0;
+}
+
+/* Add -Fp delta(x - xp) with the 3-point delta (27 nodes, weights sum to 1
+ * by construction, no renormalisation). */
+void orc_spread_point_roma(const orc_grid *g, const double xp[3], const double Fp[3],
+                           double *F)
+{
+    const orc_params *p = orc__params(g);
+    int dims[3] = {p->nx, p->ny, p->nz};
+    size_t n = (size_t)p->nx * p->ny * p->nz;
+    int lo[3];
+    for (int a = 0; a < 3; ++a)
+        lo[a] = (int)floor(xp[a]) - 1; /* nodes lo .. lo + 3 cover |x - xp| < 3/2 */
+    for (int kz = 0; kz < 4; ++kz)
+        for (int ky = 0; ky < 4; ++ky)
+            for (int kx = 0; kx < 4; ++kx) {
+                double w = orc_roma_phi(lo[0] + kx - xp[0]) * orc_roma_phi(lo[1] + ky - xp[1]) *
+                           orc_roma_phi(lo[2] + kz - xp[2]);
+                if (w == 0.0)
+                    continue;
+                int ix = ((lo[0] + kx) % dims[0] + dims[0]) % dims[0];
+                int iy = ((lo[1] + ky) % dims[1] + dims[1]) % dims[1];
+                int iz = ((lo[2] + kz) % dims[2] + dims[2]) % dims[2];
+                size_t c = (size_t)ix + (size_t)p->nx * ((size_t)iy + (size_t)p->ny * iz);
+                for (int k = 0; k < 3; ++k)
+                    F[(size_t)k * n + c] -= w * Fp[k];
+            }
+}
+
+/* Prandtl tip-loss factor for a blade element at radius r of a rotor of
+ * radius R with B blades, inflow angle phi (radians); 0 at and beyond the
+ * tip, 1 where the relative wind lies in the rotor plane. */
+double orc_tip_loss(int n_blades, double radius, double r, double phi_rad)
+{
+    if (!(r < radius))
+        return 0.0;
+    double s = fabs(sin(phi_rad));
+    if (s == 0.0)
+        return 1.0;
+    double f = 0.5 * n_blades * (radius - r) / (r * s);
+    return 2.0 / PI * acos(exp(-f));
+}
+
 /* One ALM update: kinematics, sampling, blade elements, spreading, loads. */
 void orc_alm_step(orc_grid *g)
 {
@@ -270,6 +332,11 @@ void orc_alm_step(orc_grid *g)
                 orc_blade_element(rho, wn, wt, R->chord[k], R->dl[k], R->twist[k],
                                   d->pitch_deg, d->n_polar, R->alpha, R->cl, R->cd,
                                   &Fn, &Ft, NULL);
+                if (d->tip_loss) {
+                    double Fl = orc_tip_loss(d->n_blades, d->radius, rr, atan2(wn, wt));
+                    Fn *= Fl;
+                    Ft *= Fl;
+                }
                 double Fp[3];
                 for (int a = 0; a < 3; ++a)
                     Fp[a] = Fn * (a == 0 ? 1.0 : 0.0) + Ft * et[a];
@@ -279,7 +346,10 @@ void orc_alm_step(orc_grid *g)
                 }
                 T += Fn;
                 Q += rr * Ft;
-                orc_spread_point(g, xp, Fp, d->eps, frot);
+                if (d->kernel == ORC_KERNEL_ROMA3)
+                    orc_spread_point_roma(g, xp, Fp, frot);
+                else
+                    orc_spread_point(g, xp, Fp, d->eps, frot);
             }
         }
         R->loads[0] = T;

@@ -118,3 +118,102 @@ def test_rotor_momentum_budget_and_loads(orc):
         assert loads[2] == pytest.approx(loads[1] * rot["omega_rot"], rel=1e-12)
     # a turning rotor in axial wind produces positive thrust
     assert loads[0] > 0
+
+
+# ---------------------------------------------------------------- Roma delta
+def test_roma_phi_node_values(orc):
+    """Values fixed by the closed form at the nodes and half-nodes, and the
+    continuity of the two branches at |r| = 1/2."""
+    assert orc.roma_phi(0.0) == pytest.approx(2.0 / 3.0, abs=1e-15)
+    assert orc.roma_phi(1.0) == pytest.approx(1.0 / 6.0, abs=1e-15)
+    assert orc.roma_phi(-1.0) == pytest.approx(1.0 / 6.0, abs=1e-15)
+    assert orc.roma_phi(0.5) == pytest.approx(0.5, abs=1e-15)
+    assert orc.roma_phi(0.5 + 1e-12) == pytest.approx(0.5, abs=1e-9)
+    assert orc.roma_phi(1.5) == 0.0 and orc.roma_phi(-2.0) == 0.0
+    assert orc.roma_phi(1.5 - 1e-9) == pytest.approx(0.0, abs=1e-8)
+
+
+def test_roma_phi_defining_moment_conditions(orc):
+    """Roma, Peskin and Berger define the 3-point delta by three conditions at
+    every offset r: the shifts sum to one, their first moment vanishes and
+    their squares sum to one half."""
+    rng = np.random.default_rng(7)
+    for r in np.concatenate([rng.uniform(0.0, 1.0, 50), [0.0, 0.25, 0.5, 0.75]]):
+        w = np.array([orc.roma_phi(r - j) for j in range(-2, 4)])
+        d = r - np.arange(-2, 4)
+        assert w.sum() == pytest.approx(1.0, abs=1e-14)
+        assert (d * w).sum() == pytest.approx(0.0, abs=1e-14)
+        assert (w * w).sum() == pytest.approx(0.5, abs=1e-14)
+        assert np.count_nonzero(w) <= 3
+
+
+def test_roma_spread_conserves_force_and_centre(orc):
+    n = 16
+    g = orc.Grid(n, n, n)
+    rng = np.random.default_rng(8)
+    z, y, x = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    for _ in range(6):
+        xp = rng.uniform(4, 12, 3)
+        Fp = rng.normal(0, 1, 3)
+        F = g.spread_point(xp, Fp, 0.0, kernel="roma3")
+        assert np.allclose(F.reshape(3, -1).sum(1), -Fp, rtol=1e-14, atol=1e-15)
+        w = -F[1] / Fp[1]
+        # zero first moment per axis: the centre of the weights is the point
+        cen = np.array([(w * x).sum(), (w * y).sum(), (w * z).sum()])
+        assert np.abs(cen - xp).max() < 1e-12
+        assert np.count_nonzero(w) == 27
+        assert (w >= 0).all()
+
+
+# ---------------------------------------------------------------- tip loss
+def test_tip_loss_closed_forms(orc):
+    """exp(-f) = 1/2 gives arccos(1/2) = pi/3, i.e. F = 2/3; exp(-f) = 1/sqrt(2)
+    gives F = 1/2. With f = B (R - r) / (2 r |sin phi|) the radius R that
+    makes f a chosen value is R = r + 2 r |sin phi| f / B."""
+    B, r, phi = 3, 10.0, 0.3
+    for f, F in [(np.log(2.0), 2.0 / 3.0), (0.5 * np.log(2.0), 0.5)]:
+        R = r + 2.0 * r * abs(np.sin(phi)) * f / B
+        assert orc.tip_loss(B, R, r, phi) == pytest.approx(F, abs=1e-14)
+        assert orc.tip_loss(B, R, r, -phi) == pytest.approx(F, abs=1e-14)
+    # zero at the tip, one far inboard, one for wind in the rotor plane
+    assert orc.tip_loss(3, 20.0, 20.0, 0.3) == 0.0
+    assert orc.tip_loss(3, 20.0, 0.5, 0.3) == pytest.approx(1.0, abs=1e-12)
+    assert orc.tip_loss(3, 20.0, 15.0, 0.0) == 1.0
+    # decreasing towards the tip; more blades, less loss
+    rs = np.linspace(1.0, 19.9, 40)
+    Fs = np.array([orc.tip_loss(3, 20.0, rr, 0.2) for rr in rs])
+    assert (np.diff(Fs) <= 0).all()
+    assert (np.diff(Fs[Fs < 1.0 - 1e-15]) < 0).all() and Fs[-1] < 0.5
+    assert orc.tip_loss(5, 20.0, 18.0, 0.2) > orc.tip_loss(3, 20.0, 18.0, 0.2)
+
+
+def test_tip_loss_and_roma_in_the_rotor_step(orc):
+    """Same rotor and flow: with the tip-loss factor every point force is
+    scaled by a factor in (0, 1], smallest at the outermost point; with the
+    Roma delta the momentum budget of the box still closes exactly."""
+    base = workloads.make_rotor(hub=(12.0, 15.5, 15.5), radius=8.0, n_blades=3, n_points=8,
+                                tsr=6.0, u_ref=0.05)
+    res = {}
+    for name, extra in [("plain", {}), ("tip", {"tip_loss": True}), ("roma", {"kernel": "roma3"})]:
+        rot = dict(base, **extra)
+        g = orc.Grid(32, 32, 32, omega=1.8)
+        rho = np.ones((32, 32, 32))
+        u = np.zeros((3, 32, 32, 32))
+        u[0] = 0.05
+        g.init_fields(rho, u)
+        g.set_rotor(0, rot)
+        C27 = np.array([[i % 3 - 1, (i // 3) % 3 - 1, i // 9 - 1] for i in range(27)])
+        f0 = g.get_pops().reshape(27, -1)
+        g.step(1)
+        f1 = g.get_pops().reshape(27, -1)
+        res[name] = g.rotor_loads(0, with_points=True)
+        dP = np.einsum("ia,in->a", C27, f1 - f0)
+        np.testing.assert_allclose(dP, -res[name][1].sum(0), rtol=1e-9, atol=1e-12)
+    # the first step samples the same initial field in every case
+    ratio = np.linalg.norm(res["tip"][1], axis=1) / np.linalg.norm(res["plain"][1], axis=1)
+    ratio = ratio.reshape(3, -1)
+    assert (ratio > 0).all() and (ratio <= 1 + 1e-12).all()
+    assert (np.diff(ratio, axis=1) < 0).all()
+    assert res["tip"][0][0] < res["plain"][0][0]
+    # the kernel does not change the first step's blade forces
+    np.testing.assert_allclose(res["roma"][1], res["plain"][1], rtol=1e-12, atol=1e-18)
