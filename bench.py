@@ -116,7 +116,7 @@ def measured_traffic():
                 vals[k] = v
     if vals.get("source_sha256_16") != h.hexdigest()[:16]:
         return {}
-    return {k: float(v) for k, v in vals.items() if k in ("f32", "f16", "bf16")}
+    return {k: float(v) for k, v in vals.items() if k != "source_sha256_16"}
 
 
 def cpu_baseline(sample_n=128, steps=100):
@@ -189,7 +189,8 @@ def main():
         log(f"bench: oracle {cpu['value']:.2f} MLUPS on {cpu['cores']} cores")
 
     nb = base["bytes_per_lup"]
-    traffic = measured_traffic().get("f32") if n == 512 else None
+    measured = measured_traffic() if n == 512 else {}
+    traffic = measured.get("f32")
     out = {
         "metric": "MLUPS & % HBM roofline, D3Q27 512^3: FP32 vs FP16-store(+learned closure)",
         "value": round(base["mlups"], 1),
@@ -220,7 +221,8 @@ def main():
         "variants": {k: {"mlups": round(v["mlups"], 1), "ms_per_step": round(v["ms_per_step"], 4),
                          "achieved_GBps": round(v["achieved_GBps"], 1),
                          "hbm_frac": round(v["hbm_frac"], 4), "bytes_per_lup": v["bytes_per_lup"],
-                         "ratio_vs_f32": round(v["mlups"] / base["mlups"], 3)}
+                         "ratio_vs_f32": round(v["mlups"] / base["mlups"], 3),
+                         "traffic": measured.get(k)}
                      for k, v in results.items()},
     }
     print(json.dumps(out), flush=True)

@@ -107,9 +107,17 @@ int lbm_init_fields(lbm_ctx *ctx, const double *rho, const double *u);
  * C_L and C_D on a uniform grid alpha_deg[] (ascending), interpolated
  * linearly, end values outside. Blade b sits at azimuth
  * azimuth0 + omega_rot * t + 2 pi b / n_blades, measured from +y towards +z.
- * eps is the Gaussian kernel width (support: 13 nodes per axis around the
- * nearest node). All arrays are copied. rotor_id in [0, 8). The rotor's
- * spreading box must lie inside the domain. */
+ * kernel selects the regularisation of the spread force (Sec. 2.2):
+ * LBM_KERNEL_GAUSS, the Gaussian of width eps (> 0) on 13 nodes per axis
+ * around the nearest node, renormalised to unit sum; or LBM_KERNEL_ROMA3, the
+ * 3-point discrete delta of Roma et al. (27 nodes, unit sum by construction;
+ * eps ignored). tip_loss = 1 multiplies each blade-element force by the
+ * Prandtl tip-loss factor 2/pi arccos(exp(-B (radius - r) / (2 r |sin phi|))),
+ * phi the inflow angle (the paper's Glauert-type correction, Sec. 2.2, 4).
+ * Zero-initialised trailing fields give the Gaussian without tip loss.
+ * All arrays are copied. rotor_id in [0, 8). The rotor's spreading box must
+ * lie inside the domain. */
+enum { LBM_KERNEL_GAUSS = 0, LBM_KERNEL_ROMA3 = 1 };
 typedef struct {
     double hub[3];
     double axis[3];        /* must be (1, 0, 0) */
@@ -118,6 +126,8 @@ typedef struct {
     const double *r, *chord, *twist_deg, *dl;
     int n_polar;
     const double *alpha_deg, *cl, *cd;
+    int kernel;            /* LBM_KERNEL_GAUSS or LBM_KERNEL_ROMA3 */
+    int tip_loss;          /* 0 or 1 */
 } lbm_rotor;
 int lbm_set_rotor(lbm_ctx *ctx, int rotor_id, const lbm_rotor *rotor);
 

@@ -4,6 +4,7 @@
 // trilinearly, evaluates the blade-element force and reduces thrust and
 // torque in FP64; a second kernel spreads the reaction force onto the
 // rotor's box of cells in gather form (no atomics, deterministic).
+#include "../../include/lbm.h"
 #include "lbm_access.h"
 
 namespace lbm {
@@ -23,6 +24,27 @@ __device__ __forceinline__ double polar_lookup(double a, const RotorDev &R, cons
 }
 
 __device__ __forceinline__ int wrap_any(int v, int n) { return ((v % n) + n) % n; }
+
+// 1-D factor of the 3-point discrete delta of Roma, Peskin and Berger (1999),
+// lattice units: support |r| < 3/2, shifts summing to one.
+__device__ __forceinline__ float roma_phi(float r) {
+    const float a = fabsf(r);
+    if (a <= 0.5f) return (1.0f + sqrtf(1.0f - 3.0f * a * a)) * (1.0f / 3.0f);
+    if (a < 1.5f) {
+        const float b = 1.0f - a;
+        return (5.0f - 3.0f * a - sqrtf(1.0f - 3.0f * b * b)) * (1.0f / 6.0f);
+    }
+    return 0.0f;
+}
+
+// Prandtl tip-loss factor 2/pi arccos(exp(-f)), f = B (R - r) / (2 r |sin phi|):
+// zero at and beyond the tip, one for wind in the rotor plane.
+__device__ __forceinline__ double tip_loss_factor(int B, double R, double r, double phi) {
+    if (!(r < R)) return 0.0;
+    const double s = fabs(sin(phi));
+    if (s == 0.0) return 1.0;
+    return (2.0 / PI_D) * acos(exp(-0.5 * B * (R - r) / (r * s)));
+}
 
 // Points are processed in batches of 32: workgroup (b, r) handles points
 // 32b .. 32b+31 of rotor r. Its 256 threads first stage the density and
@@ -95,18 +117,26 @@ __global__ __launch_bounds__(ALM_BLOCK) void k_alm_points(Geo g, Physics ph, Rot
                 Fn = q * (CL * wt + CD * wn) / wm;
                 Ft = q * (CL * wn - CD * wt) / wm;
             }
+            if (R.tip_loss) {
+                const double Fl = tip_loss_factor(R.n_blades, R.radius, rr, atan2(wn, wt));
+                Fn *= Fl;
+                Ft *= Fl;
+            }
             const double Fp[3] = {Fn, -Ft * st, Ft * ct};
-            // Gaussian normalisation over the 13 nodes per axis (separable)
+            // Gaussian normalisation over the 13 nodes per axis (separable);
+            // the Roma delta sums to one as it stands
             int c0[3];
             double S = 1.0;
             for (int ax = 0; ax < 3; ++ax) {
                 c0[ax] = (int)floor(xp[ax] + 0.5);
-                double sa = 0.0;
-                for (int d = -SUPPORT; d <= SUPPORT; ++d) {
-                    const double e = (c0[ax] + d) - xp[ax];
-                    sa += exp(-e * e / (R.eps * R.eps));
+                if (R.kernel == LBM_KERNEL_GAUSS) {
+                    double sa = 0.0;
+                    for (int d = -SUPPORT; d <= SUPPORT; ++d) {
+                        const double e = (c0[ax] + d) - xp[ax];
+                        sa += exp(-e * e / (R.eps * R.eps));
+                    }
+                    S *= sa;
                 }
-                S *= sa;
             }
             float *P = R.pts + (size_t)p * PT_STRIDE;
             for (int ax = 0; ax < 3; ++ax) {
@@ -165,14 +195,17 @@ __global__ __launch_bounds__(ALM_BLOCK) void k_alm_spread(const RotorDev *rots, 
     if (c >= nb) return;
     const int lx = (int)(c % B.bnx), ly = (int)((c / B.bnx) % B.bny), lz = (int)(c / ((size_t)B.bnx * B.bny));
     const int X = B.x0 + lx, Y = B.y0 + ly, Z = B.z0 + lz;
-    const float ie2 = (float)(1.0 / (R.eps * R.eps));
+    const float ie2 = R.kernel == LBM_KERNEL_GAUSS ? (float)(1.0 / (R.eps * R.eps)) : 0.0f;
+    const int half = R.half;
+    const bool roma = R.kernel == LBM_KERNEL_ROMA3;  // uniform over the grid
     float Fx = 0.f, Fy = 0.f, Fz = 0.f;
     for (int p = 0; p < npts; ++p) {
         const float *P = sp + p * PT_STRIDE;
         const int dx = X - (int)P[6], dy = Y - (int)P[7], dz = Z - (int)P[8];
-        if (abs(dx) > SUPPORT || abs(dy) > SUPPORT || abs(dz) > SUPPORT) continue;
+        if (abs(dx) > half || abs(dy) > half || abs(dz) > half) continue;
         const float ex = (float)dx - P[0], ey = (float)dy - P[1], ez = (float)dz - P[2];
-        const float w = expf(-(ex * ex + ey * ey + ez * ez) * ie2) * P[9];
+        const float w = roma ? roma_phi(ex) * roma_phi(ey) * roma_phi(ez)
+                             : expf(-(ex * ex + ey * ey + ez * ez) * ie2) * P[9];
         Fx = fmaf(w, P[3], Fx);
         Fy = fmaf(w, P[4], Fy);
         Fz = fmaf(w, P[5], Fz);

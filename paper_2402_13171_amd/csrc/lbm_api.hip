@@ -359,7 +359,14 @@ int lbm_set_rotor(lbm_ctx *c, int id, const lbm_rotor *r) {
         return fail(c, LBM_EINVAL, "n_blades*n_points must be in [1, %d]", ALM_MAX_POINTS);
     if (r->n_polar < 2 || !r->r || !r->chord || !r->twist_deg || !r->dl || !r->alpha_deg || !r->cl || !r->cd)
         return fail(c, LBM_EINVAL, "missing rotor arrays");
-    if (!(r->eps > 0.0) || !(r->radius > 0.0)) return fail(c, LBM_EINVAL, "eps and radius must be positive");
+    if (r->kernel != LBM_KERNEL_GAUSS && r->kernel != LBM_KERNEL_ROMA3)
+        return fail(c, LBM_EINVAL, "unknown spreading kernel %d", r->kernel);
+    if (r->tip_loss != 0 && r->tip_loss != 1) return fail(c, LBM_EINVAL, "tip_loss must be 0 or 1");
+    if ((r->kernel == LBM_KERNEL_GAUSS && !(r->eps > 0.0)) || !(r->radius > 0.0))
+        return fail(c, LBM_EINVAL, "eps (Gaussian kernel) and radius must be positive");
+    // support half-width in nodes around the nearest node: the Roma delta
+    // vanishes at 3/2 cells, so round(x_p) +- 1 holds all 27 of its nodes
+    const int half = r->kernel == LBM_KERNEL_ROMA3 ? 1 : SUPPORT;
     const double a0 = r->alpha_deg[0], da = (r->alpha_deg[r->n_polar - 1] - a0) / (r->n_polar - 1);
     if (!(da > 0.0)) return fail(c, LBM_EINVAL, "polar angles must ascend");
     for (int k = 0; k < r->n_polar; ++k)
@@ -371,10 +378,10 @@ int lbm_set_rotor(lbm_ctx *c, int id, const lbm_rotor *r) {
         if (!(std::fabs(r->twist_deg[k] + r->pitch_deg) < 180.0))
             return fail(c, LBM_EINVAL, "|twist + pitch| must stay below 180 degrees");
     }
-    // spreading box: every support node round(x_p) +- SUPPORT of every point
-    const int bx0 = (int)std::floor(r->hub[0] + 0.5) - SUPPORT, bx1 = (int)std::floor(r->hub[0] + 0.5) + SUPPORT;
-    const int by0 = (int)std::floor(r->hub[1] - rmax + 0.5) - SUPPORT, by1 = (int)std::floor(r->hub[1] + rmax + 0.5) + SUPPORT;
-    const int bz0 = (int)std::floor(r->hub[2] - rmax + 0.5) - SUPPORT, bz1 = (int)std::floor(r->hub[2] + rmax + 0.5) + SUPPORT;
+    // spreading box: every support node round(x_p) +- half of every point
+    const int bx0 = (int)std::floor(r->hub[0] + 0.5) - half, bx1 = (int)std::floor(r->hub[0] + 0.5) + half;
+    const int by0 = (int)std::floor(r->hub[1] - rmax + 0.5) - half, by1 = (int)std::floor(r->hub[1] + rmax + 0.5) + half;
+    const int bz0 = (int)std::floor(r->hub[2] - rmax + 0.5) - half, bz1 = (int)std::floor(r->hub[2] + rmax + 0.5) + half;
     if (bx0 < 0 || by0 < 0 || bz0 < 0 || bx1 >= c->cfg.nx || by1 >= c->cfg.ny || bz1 >= c->cfg.nz)
         return fail(c, LBM_EINVAL, "rotor spreading box [%d,%d]x[%d,%d]x[%d,%d] leaves the domain", bx0, bx1, by0, by1,
                     bz0, bz1);
@@ -417,6 +424,10 @@ int lbm_set_rotor(lbm_ctx *c, int id, const lbm_rotor *r) {
     D.azimuth0 = r->azimuth0;
     D.pitch_deg = r->pitch_deg;
     D.eps = r->eps;
+    D.radius = r->radius;
+    D.kernel = r->kernel;
+    D.tip_loss = r->tip_loss;
+    D.half = half;
     D.n_blades = r->n_blades;
     D.n_points = np;
     D.n_polar = r->n_polar;

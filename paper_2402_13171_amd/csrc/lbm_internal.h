@@ -60,8 +60,11 @@ struct Physics {
 // Per-rotor device description used by the actuator-line kernels.
 struct RotorDev {
     double hub[3];
-    double omega_rot, azimuth0, pitch_deg, eps;
+    double omega_rot, azimuth0, pitch_deg, eps, radius;
     int n_blades, n_points, n_polar;
+    int kernel;    // LBM_KERNEL_GAUSS / LBM_KERNEL_ROMA3
+    int tip_loss;  // multiply blade-element forces by the Prandtl factor
+    int half;      // spreading support: nodes nearest(x_p) +- half per axis
     double alpha0, dalpha;
     const double *r, *chord, *twist, *dl;     // n_points
     const float *cl, *cd;                     // n_polar

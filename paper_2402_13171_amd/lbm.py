@@ -56,7 +56,11 @@ class Rotor(C.Structure):
                 ("eps", C.c_double), ("pitch_deg", C.c_double),
                 ("n_blades", C.c_int), ("n_points", C.c_int),
                 ("r", _D), ("chord", _D), ("twist_deg", _D), ("dl", _D),
-                ("n_polar", C.c_int), ("alpha_deg", _D), ("cl", _D), ("cd", _D)]
+                ("n_polar", C.c_int), ("alpha_deg", _D), ("cl", _D), ("cd", _D),
+                ("kernel", C.c_int), ("tip_loss", C.c_int)]
+
+
+KERNELS = {"gauss": 0, "roma3": 1}
 
 
 _lib = None
@@ -223,6 +227,8 @@ class Lbm:
         d.twist_deg, d.dl = _p(arrs["twist_deg"]), _p(arrs["dl"])
         d.n_polar = len(pol["alpha_deg"])
         d.alpha_deg, d.cl, d.cd = _p(pol["alpha_deg"]), _p(pol["cl"]), _p(pol["cd"])
+        d.kernel = KERNELS[rot.get("kernel", "gauss")]
+        d.tip_loss = int(bool(rot.get("tip_loss", False)))
         self._check(lib().lbm_set_rotor(self._ctx, rid, C.byref(d)))
         self._npts[rid] = d.n_blades * d.n_points
 

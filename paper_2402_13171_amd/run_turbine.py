@@ -6,7 +6,8 @@
 
 single: 256 x 128 x 128, FP32, uniform inflow 0.05 at x = 0, zero-gradient
 outflow, periodic y/z, one 3-blade rotor (diameter 32, TSR 7, 3 x 32 points,
-Gaussian eps = 2) at x = 64, 2000 steps. Reports MLUPS with the rotor and
+Gaussian eps = 2, or --kernel roma3 for the Roma 3-point delta, --tip-loss
+for the Prandtl factor) at x = 64, 2000 steps. Reports MLUPS with the rotor and
 without it (the paper's way of isolating the turbine overhead, Sec. 4.3,
 Table 1), the thrust/torque/power time series, and the final normal and
 tangential force per blade point.
@@ -43,10 +44,13 @@ def timed_steps(sim, n):
 
 def single(args, log):
     nx, ny, nz = 256, 128, 128
-    rot = workloads.single_turbine_rotor()
+    rot = dict(workloads.single_turbine_rotor(), kernel=args.kernel, tip_loss=args.tip_loss)
     u0 = np.zeros((3, nz, ny, nx))
     u0[0] = 0.05
-    out = {"workload": "single turbine 256x128x128 FP32, inflow 0.05, rotor D=32 TSR 7, eps 2"}
+    spread = "eps 2 Gaussian" if args.kernel == "gauss" else "Roma 3-point delta"
+    out = {"workload": f"single turbine 256x128x128 FP32, inflow 0.05, rotor D=32 TSR 7, {spread}"
+                       + (", Prandtl tip loss" if args.tip_loss else ""),
+           "kernel": args.kernel, "tip_loss": args.tip_loss}
     # without the rotor
     sim = Lbm(nx, ny, nz, omega=args.omega, bc_x="inout", u_in=(0.05, 0, 0))
     sim.init_fields(np.ones((nz, ny, nx)), u0)
@@ -137,6 +141,9 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--omega", type=float, default=1.9)
     ap.add_argument("--weights", default=None)
+    ap.add_argument("--kernel", choices=["gauss", "roma3"], default="gauss",
+                    help="force spreading kernel (single case)")
+    ap.add_argument("--tip-loss", action="store_true", help="Prandtl tip-loss factor (single case)")
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
     if a.steps is None:

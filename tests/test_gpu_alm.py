@@ -65,6 +65,24 @@ def test_rotor_in_periodic_box():
     assert np.linalg.norm(ug - ur, axis=0).max() <= 1e-5 * np.linalg.norm(ur, axis=0).max()
 
 
+@pytest.mark.parametrize("kernel,tip", [("roma3", False), ("gauss", True), ("roma3", True)])
+def test_rotor_options_match_oracle(kernel, tip):
+    """Roma 3-point delta spreading and the Prandtl tip-loss factor, alone and
+    together: loads every step and fields after 9 steps against the oracle."""
+    _need_gpu()
+    rot = workloads.make_rotor(hub=(20.0, 23.5, 24.0), radius=8.0, n_blades=3, n_points=8,
+                               tsr=0.02 * 8 / 0.05, u_ref=0.05)
+    rot = dict(rot, kernel=kernel, tip_loss=tip)
+    sim, ref, hist = run_pair((48, 48, 48), [rot], 9)
+    w = check_hist(hist, 2e-5)
+    _, ug = sim.fields()
+    _, ur = ref.fields()
+    err = np.linalg.norm(ug - ur, axis=0).max() / np.linalg.norm(ur, axis=0).max()
+    print(f"rotor {kernel} tip_loss={tip}: worst load error {w:.2e}, field eps_max {err:.2e}")
+    assert err <= 1e-5
+    assert np.abs(sim.pops() - ref.get_pops()).max() <= 2e-6
+
+
 def test_two_rotors_inflow_outflow():
     _need_gpu()
     rots = [workloads.make_rotor(hub=(16.0, 16.5, 15.5), radius=6.0, n_blades=3, n_points=6,
