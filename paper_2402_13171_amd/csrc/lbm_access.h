@@ -180,6 +180,17 @@ struct Unroll32 {
         Store<T>::st((T *)(plane(g, I) + boff), o[I]);
         Unroll32<T, I + 1>::write_periodic(g, xs, rows, o);
     }
+    // the nine directions with c_x = CX only
+    template <int CX>
+    static __device__ __forceinline__ void write_periodic_cx(const Geo &g, const uint32_t *xs, const uint32_t *rows,
+                                                             const float *o) {
+        constexpr int cx = cx_of(I), cy = cy_of(I), cz = cz_of(I);
+        if constexpr (cx == CX) {
+            const uint32_t boff = (rows[(1 + cy) + 3 * (1 + cz)] + xs[1 + cx]) * (uint32_t)sizeof(T);
+            Store<T>::st((T *)(plane(g, I) + boff), o[I]);
+        }
+        Unroll32<T, I + 1>::template write_periodic_cx<CX>(g, xs, rows, o);
+    }
 };
 template <typename T>
 struct Unroll32<T, 27> {
@@ -187,6 +198,9 @@ struct Unroll32<T, 27> {
     static __device__ __forceinline__ void write_swap_local(const Geo &, uint32_t, const float *) {}
     static __device__ __forceinline__ void read_periodic(const Geo &, const uint32_t *, const uint32_t *, float *) {}
     static __device__ __forceinline__ void write_periodic(const Geo &, const uint32_t *, const uint32_t *, const float *) {}
+    template <int CX>
+    static __device__ __forceinline__ void write_periodic_cx(const Geo &, const uint32_t *, const uint32_t *,
+                                                             const float *) {}
 };
 
 template <typename T>

@@ -1,8 +1,9 @@
 // Actuator-line kernels (Sec. 2.2 of the waLBerla-wind paper): per step, one
-// workgroup per rotor computes blade-point kinematics, stages the density and
+// workgroup per 32 blade points computes their kinematics, stages the density and
 // velocity of the 8 cells around every point in LDS, interpolates them
 // trilinearly, evaluates the blade-element force and reduces thrust and
-// torque in FP64; a second kernel spreads the reaction force onto the
+// torque per batch of points in FP64 (the host adds the batch partials when
+// the loads are read); a second kernel spreads the reaction force onto the
 // rotor's box of cells in gather form (no atomics, deterministic).
 #include "../../include/lbm.h"
 #include "lbm_access.h"
@@ -50,9 +51,10 @@ __device__ __forceinline__ double tip_loss_factor(int B, double R, double r, dou
 // 32b .. 32b+31 of rotor r. Its 256 threads first stage the density and
 // velocity of the 8 cells around each of the 32 points in LDS (thread ->
 // point, corner), then 32 threads interpolate and evaluate the blade
-// elements. Each workgroup leaves FP64 partial thrust and torque; k_alm_loads
-// adds the partials in a fixed order.
+// elements. Each workgroup leaves FP64 partial thrust and torque; the host
+// adds the partials in batch order when the loads are read.
 constexpr int ALM_BATCH = ALM_BLOCK / 8;
+static_assert(ALM_BATCH == ALM_BATCH_PTS, "batch size shared with the host-side load sum");
 constexpr int ALM_MAX_BATCHES = ALM_MAX_PTS / ALM_BATCH;
 
 template <typename T, int PAR>
@@ -130,12 +132,14 @@ __global__ __launch_bounds__(ALM_BLOCK) void k_alm_points(Geo g, Physics ph, Rot
             for (int ax = 0; ax < 3; ++ax) {
                 c0[ax] = (int)floor(xp[ax] + 0.5);
                 if (R.kernel == LBM_KERNEL_GAUSS) {
-                    double sa = 0.0;
+                    // FP32 terms, the precision of the spread weights themselves
+                    const float ie2 = (float)(1.0 / (R.eps * R.eps)), e0 = (float)(c0[ax] - xp[ax]);
+                    float sa = 0.0f;
                     for (int d = -SUPPORT; d <= SUPPORT; ++d) {
-                        const double e = (c0[ax] + d) - xp[ax];
-                        sa += exp(-e * e / (R.eps * R.eps));
+                        const float e = e0 + (float)d;
+                        sa += expf(-e * e * ie2);
                     }
-                    S *= sa;
+                    S *= (double)sa;
                 }
             }
             float *P = R.pts + (size_t)p * PT_STRIDE;
@@ -165,21 +169,6 @@ __global__ __launch_bounds__(ALM_BLOCK) void k_alm_points(Geo g, Physics ph, Rot
         R.loads[3 + 2 * blockIdx.x] = s_red[0][0];
         R.loads[4 + 2 * blockIdx.x] = s_red[0][1];
     }
-}
-
-// thrust, torque, power of each rotor from the batch partials, in batch order
-__global__ void k_alm_loads(RotorDev *rots) {
-    RotorDev &R = rots[blockIdx.x];
-    if (threadIdx.x != 0) return;
-    const int nb = (R.n_blades * R.n_points + ALM_BATCH - 1) / ALM_BATCH;
-    double T = 0.0, Q = 0.0;
-    for (int b = 0; b < nb; ++b) {
-        T += R.loads[3 + 2 * b];
-        Q += R.loads[4 + 2 * b];
-    }
-    R.loads[0] = T;
-    R.loads[1] = Q;
-    R.loads[2] = Q * R.omega_rot;
 }
 
 // Gather-form spreading over one rotor's box: F(X) = sum_p (-F_p) eta(X - x_p) / W_p
@@ -224,7 +213,6 @@ static void alm_t(const Geo &g, const Physics &ph, const RotorDev *h_rots, Rotor
         nb = b > nb ? b : nb;
     }
     k_alm_points<T, PAR><<<dim3(nb, nrot), ALM_BLOCK, 0, s>>>(g, ph, d_rots, t);
-    k_alm_loads<<<nrot, 64, 0, s>>>(d_rots);
     for (int r = 0; r < nrot; ++r) {
         const size_t nb = (size_t)h_rots[r].box.bnx * h_rots[r].box.bny * h_rots[r].box.bnz;
         k_alm_spread<<<(unsigned)((nb + ALM_BLOCK - 1) / ALM_BLOCK), ALM_BLOCK, 0, s>>>(d_rots, r);

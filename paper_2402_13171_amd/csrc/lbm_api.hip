@@ -125,11 +125,16 @@ Physics physics_of(const lbm_ctx *c) {
     return ph;
 }
 
-// The fast stream-collide path needs an all-periodic box and 32-bit byte
-// offsets within one population plane; everything else takes the general path.
+// The fast stream-collide path needs 32-bit byte offsets within one
+// population plane; with them, a periodic box runs it everywhere and an open
+// one on every cell off the z walls (odd steps). Otherwise: the general path.
 bool general_bc(const lbm_ctx *c) {
     return c->cfg.bc_x != LBM_BC_PERIODIC || c->cfg.bc_z_lo != LBM_BC_PERIODIC || c->cfg.bc_z_hi != LBM_BC_PERIODIC ||
            c->P * c->esize >= ((size_t)1 << 32);
+}
+static int sc_mode(const lbm_ctx *c) {
+    if (c->P * c->esize >= ((size_t)1 << 32)) return SC_GENERAL;
+    return general_bc(c) ? SC_SPLIT : SC_FAST;
 }
 
 int ensure_stage(lbm_ctx *c, size_t bytes) {
@@ -504,7 +509,7 @@ int lbm_step(lbm_ctx *c, int nsteps) {
     if (nsteps < 0) return fail(c, LBM_EINVAL, "negative step count");
     if (c->cfg.closure == LBM_CLOSURE_MLP && !c->mlp_set) return fail(c, LBM_ESTATE, "closure weights not set");
     const int st = (int)c->cfg.storage;
-    const bool bcg = general_bc(c);
+    const int mode = sc_mode(c);
     int *flag = (int *)((char *)c->aux + c->off_flag);
     double *part = (double *)((char *)c->aux + c->off_part);
     // relative mass drift that counts as a failure: well above the drift that
@@ -529,7 +534,7 @@ int lbm_step(lbm_ctx *c, int nsteps) {
         g = geo_of(c);
         if (nrot > 0 && launch_alm(st, c->parity, g, ph, c->h_rots.data(), c->d_rots, nrot, c->t, c->stream))
             return fail(c, LBM_EHIP, "actuator-line launch failed");
-        if (launch_stream_collide(st, c->parity, (int)c->cfg.closure, bcg, frc, c->general_rates, g, ph, c->stream))
+        if (launch_stream_collide(st, c->parity, (int)c->cfg.closure, mode, frc, c->general_rates, g, ph, c->stream))
             return fail(c, LBM_EHIP, "stream-collide launch failed");
         c->parity ^= 1;
         c->t += 1;
@@ -636,11 +641,24 @@ int lbm_rotor_loads(lbm_ctx *c, int id, double out[3], double *pt_force) {
     if (id < 0 || id >= MAX_ROTORS || !out) return fail(c, LBM_EINVAL, "bad rotor id or null output");
     RotorHost &R = c->rot[id];
     if (!R.on) return fail(c, LBM_EINVAL, "rotor %d not set", id);
-    HIPCHK(c, hipMemcpyAsync(out, R.d_loads, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    // the step leaves FP64 partial thrust and torque per batch of 32 points;
+    // they are added here in batch order (deterministic, no extra kernel on
+    // the step's critical path)
+    double part[ALM_LOADS_LEN];
+    HIPCHK(c, hipMemcpyAsync(part, R.d_loads, sizeof(part), hipMemcpyDeviceToHost, c->stream));
     if (pt_force)
         HIPCHK(c, hipMemcpyAsync(pt_force, R.d_ptf, 3 * (size_t)R.npts * sizeof(double), hipMemcpyDeviceToHost,
                                  c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    const int nb = (R.npts + ALM_BATCH_PTS - 1) / ALM_BATCH_PTS;
+    double T = 0.0, Q = 0.0;
+    for (int b = 0; b < nb; ++b) {
+        T += part[3 + 2 * b];
+        Q += part[4 + 2 * b];
+    }
+    out[0] = T;
+    out[1] = Q;
+    out[2] = Q * R.dev.omega_rot;
     return LBM_OK;
 }
 

@@ -44,6 +44,9 @@ struct Geo {
     const float *uin_rd; // inlet velocity plane [3][ny*nz] of the streaming a swapped-layout read completes
     const float *uin_wr; // inlet velocity plane of the current step (odd-step inlet writes)
     void *ghost;         // outflow ghost plane [9][ny*nz] (storage type)
+    // z planes 0 / nz-1 that a fast-path launch leaves to the boundary-cell
+    // kernel (0 outside that split)
+    int skip_zlo, skip_zhi;
 };
 
 struct Physics {
@@ -80,7 +83,12 @@ struct RotorDev {
 constexpr int PT_STRIDE = 10;
 
 // Kernel launchers (defined in the .hip files).
-int launch_stream_collide(int storage, int parity, int closure, bool general_bc, bool force,
+// mode: SC_FAST (periodic box, 32-bit offsets), SC_GENERAL (boundary rules
+// everywhere), SC_SPLIT (boundary rules, 32-bit offsets valid: odd steps run
+// the fast path, with the x inflow/outflow rules applied per lane, on all
+// cells off the z walls, and the general path on the wall planes)
+enum { SC_FAST = 0, SC_GENERAL = 1, SC_SPLIT = 2 };
+int launch_stream_collide(int storage, int parity, int closure, int mode, bool force,
                           bool general_rates, const Geo &g, const Physics &ph, hipStream_t s);
 int launch_init_tgv(int storage, const Geo &g, double u0, double k, double rho0, hipStream_t s);
 int launch_init_eq(int storage, const Geo &g, const double *rho, const double *u, size_t cell0,
@@ -102,7 +110,8 @@ int launch_check(int storage, int parity, const Geo &g, const Physics &ph, doubl
 int launch_alm(int storage, int parity, const Geo &g, const Physics &ph, const RotorDev *h_rots,
                RotorDev *d_rots, int nrot, long t, hipStream_t s);
 constexpr int ALM_MAX_POINTS = 512;
-constexpr int ALM_LOADS_LEN = 3 + 2 * (ALM_MAX_POINTS / 32);
+constexpr int ALM_BATCH_PTS = 32;  // actuator points per workgroup of k_alm_points
+constexpr int ALM_LOADS_LEN = 3 + 2 * (ALM_MAX_POINTS / ALM_BATCH_PTS);
 constexpr int RED_NBLOCKS = 1024;   // reduction grid (fixed: deterministic sums)
 constexpr int RED_NMOM = 6;
 

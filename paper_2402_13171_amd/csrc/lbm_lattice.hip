@@ -123,24 +123,43 @@ __device__ __forceinline__ void periodic_offsets(const Geo &g, int x, int y, int
         for (int a = 0; a < 3; ++a) rows[a + 3 * b] = zs[b] + ys[a];
 }
 
-template <typename T, int PAR, int CL, bool BCG, bool FRC, bool GR>
-__global__ __launch_bounds__(256) void k_stream_collide(Geo g, Physics ph, unsigned gx, unsigned gy, unsigned total,
-                                                        unsigned tw_log2) {
-    const unsigned tile = xcd_tile(blockIdx.x, total);
-    const unsigned tw = 1u << tw_log2, th = 256u >> tw_log2;
-    const int x0 = (int)((tile % gx) * tw + (threadIdx.x & (tw - 1)));
-    const int y0 = (int)(((tile / gx) % gy) * th + (threadIdx.x >> tw_log2));
-    const int z = (int)(tile / (gx * gy));
-    // the learned closure runs on the matrix cores, which need every lane of
-    // the wave: out-of-range lanes then recompute the nearest edge cell of the
-    // row / column and store nothing
-    const bool valid = x0 < g.nx && y0 < g.ny;
+// Odd-step sources outside the box in x for a cell off the z walls (z wraps
+// if periodic): x = -1 gives the inlet equilibrium, x = nx the ghost plane.
+// The fast path has already loaded in-box values from the wrapped positions;
+// the lanes at x = 0 and x = nx-1 overwrite those nine values.
+template <typename T>
+__device__ __forceinline__ void open_x_sources(const Geo &g, int x, int y, int z, float *d) {
+    if (x == 0) {
+#pragma unroll
+        for (int I = 2; I < 27; I += 3) {  // c_x = +1: source at x = -1
+            const int sy = wrapi(y - cy_of(I), g.ny), sz = wrapi(z - cz_of(I), g.nz);
+            d[I] = inlet_dev(g, g.uin_rd, I, sy, sz);
+        }
+    }
+    if (x == g.nx - 1) {
+        const T *G = (const T *)g.ghost;
+#pragma unroll
+        for (int I = 0; I < 27; I += 3) {  // c_x = -1: source at x = nx
+            const int sy = wrapi(y - cy_of(I), g.ny), sz = wrapi(z - cz_of(I), g.nz);
+            d[I] = Store<T>::ld(G + (size_t)(I / 3) * g.ny * g.nz + sy + (size_t)g.ny * sz);
+        }
+    }
+}
+
+// Update of one cell (x, y, z) given by the launch: read, collide, write.
+// valid = false: a lane without a cell of its own; it returns at once, except
+// in the learned-closure variant, whose matrix-core instructions need every
+// lane of the wave: there it computes on (x, y, z) (a valid neighbour cell)
+// and stores nothing. mlp_lds: the workgroup's LDS copy of the network, its
+// DMA started by the caller (mlp_stage_lds).
+// XO (odd fast path only): x inflow/outflow rules per lane; the reads of the
+// x = 0 and x = nx-1 lanes from outside the box are replaced by the inlet
+// equilibrium and the ghost plane, their pushes out of the box dropped, and
+// the slots no fluid cell pushes filled (odd_boundary_extras).
+template <typename T, int PAR, int CL, bool BCG, bool FRC, bool GR, bool XO = false>
+__device__ __forceinline__ void cell_update(const Geo &g, const Physics &ph, int x, int y, int z, bool valid,
+                                            MlpLds &mlp_lds) {
     if (CL != CL_MLP && !valid) return;
-    // network operands: DMA into LDS now, in flight with the population loads
-    __shared__ MlpLds mlp_lds;
-    if (CL == CL_MLP) mlp_stage_lds(ph.mlp, &mlp_lds);
-    const int x = CL == CL_MLP ? min(x0, g.nx - 1) : x0;
-    const int y = CL == CL_MLP ? min(y0, g.ny - 1) : y0;
     const size_t cell = cidx(g, x, y, z);
     // fast path (no boundary rules): 32-bit offsets, see Unroll32
     const uint32_t cell32 = (uint32_t)cell;
@@ -152,6 +171,7 @@ __global__ __launch_bounds__(256) void k_stream_collide(Geo g, Physics ph, unsig
     } else if (!BCG) {
         periodic_offsets(g, x, y, z, xs, rows);
         Unroll32<T, 0>::read_periodic(g, xs, rows, d);
+        if (XO) open_x_sources<T>(g, x, y, z, d);
     } else {
         Unroll<T, 0>::read_sw(g, x, y, z, d);
     }
@@ -204,16 +224,64 @@ __global__ __launch_bounds__(256) void k_stream_collide(Geo g, Physics ph, unsig
                 Store<T>::st(G + (size_t)(J / 3) * g.ny * g.nz + y + (size_t)g.ny * z, o[J]);
         }
     } else if (!BCG) {
-        Unroll32<T, 0>::write_periodic(gw, xs, rows, o);
+        if (XO) {
+            // pushes out of the box through x are dropped
+            if (x != 0) Unroll32<T, 0>::template write_periodic_cx<-1>(gw, xs, rows, o);
+            Unroll32<T, 0>::template write_periodic_cx<0>(gw, xs, rows, o);
+            if (x != g.nx - 1) Unroll32<T, 0>::template write_periodic_cx<1>(gw, xs, rows, o);
+            odd_boundary_extras<T>(g, x, y, z, o);
+        } else {
+            Unroll32<T, 0>::write_periodic(gw, xs, rows, o);
+        }
     } else {
         Unroll<T, 0>::write_push(g, x, y, z, o);
         if (g.bc_x == BC_INOUT) odd_boundary_extras<T>(g, x, y, z, o);
     }
 }
 
+
+template <typename T, int PAR, int CL, bool BCG, bool FRC, bool GR, bool XO = false>
+__global__ __launch_bounds__(256) void k_stream_collide(Geo g, Physics ph, unsigned gx, unsigned gy, unsigned total,
+                                                        unsigned tw_log2) {
+    const unsigned tile = xcd_tile(blockIdx.x, total);
+    const unsigned tw = 1u << tw_log2, th = 256u >> tw_log2;
+    const int x0 = (int)((tile % gx) * tw + (threadIdx.x & (tw - 1)));
+    const int y0 = (int)(((tile / gx) % gy) * th + (threadIdx.x >> tw_log2));
+    const int z = (int)(tile / (gx * gy));
+    // z planes left to the boundary-cell kernel: whole workgroups
+    if ((g.skip_zlo && z == 0) || (g.skip_zhi && z == g.nz - 1)) return;
+    const bool valid = x0 < g.nx && y0 < g.ny;
+    if (CL != CL_MLP && !valid) return;
+    // closure variant: lanes without a cell recompute the nearest cell of their row
+    const int x = CL == CL_MLP ? min(x0, g.nx - 1) : x0;
+    const int y = CL == CL_MLP ? min(y0, g.ny - 1) : y0;
+    // network operands: DMA into LDS now, in flight with the population loads
+    __shared__ MlpLds mlp_lds;
+    if (CL == CL_MLP) mlp_stage_lds(ph.mlp, &mlp_lds);
+    cell_update<T, PAR, CL, BCG, FRC, GR, XO>(g, ph, x, y, z, valid, mlp_lds);
+}
+
+// Odd step on the z wall planes (z = 0 and / or nz-1, all x and y) with the
+// general boundary rules; pairs with a fast-path launch that skips them.
+template <typename T, int CL, bool FRC>
+__global__ __launch_bounds__(256) void k_stream_collide_walls(Geo g, Physics ph, unsigned nlo, unsigned nhi) {
+    // nlo / nhi: cells of the z = 0 / z = nz-1 plane to update (nx ny or 0)
+    const unsigned nb = nlo + nhi;
+    const unsigned b0 = blockIdx.x * 256u + threadIdx.x;
+    const bool valid = b0 < nb;
+    if (CL != CL_MLP && !valid) return;
+    const unsigned b = valid ? b0 : nb - 1;
+    const bool lo = b < nlo;
+    const unsigned r = lo ? b : b - nlo;
+    const int x = (int)(r % (unsigned)g.nx), y = (int)(r / (unsigned)g.nx), z = lo ? 0 : g.nz - 1;
+    __shared__ MlpLds mlp_lds;
+    if (CL == CL_MLP) mlp_stage_lds(ph.mlp, &mlp_lds);
+    cell_update<T, 1, CL, true, FRC, false>(g, ph, x, y, z, valid, mlp_lds);
+}
+
 // ------------------------------------------------------------ dispatch
 template <typename T, int PAR, int CL>
-static void launch_sc(bool bcg, bool frc, bool gr, const Geo &g, const Physics &ph, hipStream_t s) {
+static void launch_sc(int mode, bool frc, bool gr, const Geo &g, const Physics &ph, hipStream_t s) {
     const unsigned twl = g.nx >= 256 ? 8u : (g.nx >= 128 ? 7u : 6u);
     const unsigned tw = 1u << twl, th = 256u >> twl;
     const unsigned gx = (g.nx + tw - 1) / tw, gy = (g.ny + th - 1) / th, total = gx * gy * (unsigned)g.nz;
@@ -222,39 +290,62 @@ static void launch_sc(bool bcg, bool frc, bool gr, const Geo &g, const Physics &
     if (gr) {
         if (frc) k_stream_collide<T, PAR, CL, true, true, true><<<grd, blk, 0, s>>>(g, ph, gx, gy, total, twl);
         else k_stream_collide<T, PAR, CL, true, false, true><<<grd, blk, 0, s>>>(g, ph, gx, gy, total, twl);
-    } else if (bcg) {
+    } else if (mode == SC_GENERAL || (mode == SC_SPLIT && PAR == 0)) {
         if (frc) k_stream_collide<T, PAR, CL, true, true, false><<<grd, blk, 0, s>>>(g, ph, gx, gy, total, twl);
         else k_stream_collide<T, PAR, CL, true, false, false><<<grd, blk, 0, s>>>(g, ph, gx, gy, total, twl);
-    } else {
+    } else if (mode == SC_FAST) {
         if (frc) k_stream_collide<T, PAR, CL, false, true, false><<<grd, blk, 0, s>>>(g, ph, gx, gy, total, twl);
         else k_stream_collide<T, PAR, CL, false, false, false><<<grd, blk, 0, s>>>(g, ph, gx, gy, total, twl);
+    } else if constexpr (PAR == 1) {
+        // odd step of an open domain: every cell off the z walls on the fast
+        // path, the x inflow/outflow rules applied per lane; then the wall
+        // planes with the general rules. The two sets own disjoint slots.
+        Geo gi = g;
+        gi.skip_zlo = g.bc_zlo != BC_PERIODIC;
+        gi.skip_zhi = g.bc_zhi != BC_PERIODIC;
+        const bool xo = g.bc_x == BC_INOUT;
+        if (frc) {
+            if (xo) k_stream_collide<T, PAR, CL, false, true, false, true><<<grd, blk, 0, s>>>(gi, ph, gx, gy, total, twl);
+            else k_stream_collide<T, PAR, CL, false, true, false><<<grd, blk, 0, s>>>(gi, ph, gx, gy, total, twl);
+        } else {
+            if (xo) k_stream_collide<T, PAR, CL, false, false, false, true><<<grd, blk, 0, s>>>(gi, ph, gx, gy, total, twl);
+            else k_stream_collide<T, PAR, CL, false, false, false><<<grd, blk, 0, s>>>(gi, ph, gx, gy, total, twl);
+        }
+        const unsigned nxy = (unsigned)g.nx * (unsigned)g.ny;
+        const unsigned nlo = gi.skip_zlo ? nxy : 0u, nhi = gi.skip_zhi ? nxy : 0u;
+        if (nlo + nhi > 0) {
+            const dim3 gw((nlo + nhi + 255u) / 256u, 1, 1);
+            if (frc) k_stream_collide_walls<T, CL, true><<<gw, blk, 0, s>>>(gi, ph, nlo, nhi);
+            else k_stream_collide_walls<T, CL, false><<<gw, blk, 0, s>>>(gi, ph, nlo, nhi);
+        }
     }
 }
 
 template <typename T, int PAR>
-static int launch_sc_cl(int closure, bool bcg, bool frc, bool gr, const Geo &g, const Physics &ph, hipStream_t s) {
+static int launch_sc_cl(int closure, int mode, bool frc, bool gr, const Geo &g, const Physics &ph, hipStream_t s) {
     switch (closure) {
-        case CL_NONE: launch_sc<T, PAR, CL_NONE>(bcg, frc, gr, g, ph, s); return 0;
-        case CL_SMAG: launch_sc<T, PAR, CL_SMAG>(bcg, frc, gr, g, ph, s); return 0;
-        case CL_MLP: launch_sc<T, PAR, CL_MLP>(bcg, frc, gr, g, ph, s); return 0;
+        case CL_NONE: launch_sc<T, PAR, CL_NONE>(mode, frc, gr, g, ph, s); return 0;
+        case CL_SMAG: launch_sc<T, PAR, CL_SMAG>(mode, frc, gr, g, ph, s); return 0;
+        case CL_MLP: launch_sc<T, PAR, CL_MLP>(mode, frc, gr, g, ph, s); return 0;
         default: return -1;
     }
 }
 
 template <typename T>
-static int launch_sc_par(int parity, int closure, bool bcg, bool frc, bool gr, const Geo &g, const Physics &ph,
+static int launch_sc_par(int parity, int closure, int mode, bool frc, bool gr, const Geo &g, const Physics &ph,
                          hipStream_t s) {
-    return parity == 0 ? launch_sc_cl<T, 0>(closure, bcg, frc, gr, g, ph, s)
-                       : launch_sc_cl<T, 1>(closure, bcg, frc, gr, g, ph, s);
+    return parity == 0 ? launch_sc_cl<T, 0>(closure, mode, frc, gr, g, ph, s)
+                       : launch_sc_cl<T, 1>(closure, mode, frc, gr, g, ph, s);
 }
 
-int launch_stream_collide(int storage, int parity, int closure, bool general_bc, bool force, bool general_rates,
+int launch_stream_collide(int storage, int parity, int closure, int mode, bool force, bool general_rates,
                           const Geo &g, const Physics &ph, hipStream_t s) {
+    if (mode != SC_FAST && mode != SC_GENERAL && mode != SC_SPLIT) return -1;
     int rc;
     switch (storage) {
-        case 0: rc = launch_sc_par<float>(parity, closure, general_bc, force, general_rates, g, ph, s); break;
-        case 1: rc = launch_sc_par<__half>(parity, closure, general_bc, force, general_rates, g, ph, s); break;
-        case 2: rc = launch_sc_par<bf16_t>(parity, closure, general_bc, force, general_rates, g, ph, s); break;
+        case 0: rc = launch_sc_par<float>(parity, closure, mode, force, general_rates, g, ph, s); break;
+        case 1: rc = launch_sc_par<__half>(parity, closure, mode, force, general_rates, g, ph, s); break;
+        case 2: rc = launch_sc_par<bf16_t>(parity, closure, mode, force, general_rates, g, ph, s); break;
         default: return -1;
     }
     if (rc) return rc;

@@ -1,6 +1,6 @@
 """Wind-turbine runs of the actuator-line path.
 
-    python -m paper_2402_13171_amd.run_turbine single --out results/single_turbine.json
+    python -m paper_2402_13171_amd.run_turbine single --kernel gauss --out results/single_turbine_gauss.json
     python -m paper_2402_13171_amd.run_turbine row --weights results/closure_weights.npy \
         --out results/turbine_row.json
 
@@ -151,7 +151,7 @@ def main(argv=None):
     t_start = time.time()
     log = lambda *m: print(f"[{time.time() - t_start:7.1f}s]", *m, flush=True)
     res = single(a, log) if a.case == "single" else row(a, log)
-    out = a.out or f"results/{'single_turbine' if a.case == 'single' else 'turbine_row'}.json"
+    out = a.out or (f"results/single_turbine_{a.kernel}{'_tiploss' if a.tip_loss else ''}.json" if a.case == 'single' else "results/turbine_row.json")
     os.makedirs(os.path.dirname(out) or ".", exist_ok=True)
     with open(out, "w") as fh:
         json.dump(res, fh)

@@ -110,20 +110,39 @@ def test_single_turbine_full_size_first_steps():
     assert T > 0 and Q > 0  # the rotor is driven by the wind and thrusts downstream
 
 
-@pytest.mark.parametrize("storage,tol", [("f32", 2e-6)])
-def test_turbine_row_analogue_sheared_turbulent_inflow(storage, tol):
+def _closure_blob(seed=10):
+    from oracle import mlp_ref
+    rng = np.random.default_rng(seed)
+    blob = mlp_ref.init_blob(seed=seed, mu=rng.normal(0, 1e-3, 6), sigma=rng.uniform(0.5, 2.0, 6) * 1e-3,
+                             nu_scale=2e-3)
+    return blob.astype(np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("storage,closure,tol,ltol", [("f32", "none", 2e-6, 2e-5), ("f32", "mlp", 2e-6, 2e-5),
+                                                      ("f16", "mlp", 2e-4, 2e-3)])
+def test_turbine_row_analogue_sheared_turbulent_inflow(storage, closure, tol, ltol):
     """Reduced turbine-row case: 96 x 32 x 32, ground wall (bounce-back), free-slip
     top, sheared inflow plus a frozen turbulence box convected at the hub
-    speed, one rotor; populations and loads against the oracle for 12 steps."""
+    speed, one rotor, optionally FP16 storage and the learned closure (oracle
+    in its bfloat16-emulating mode); populations and loads against the oracle
+    for 12 steps."""
     _need_gpu()
     from paper_2402_13171_amd.lbm import Lbm
     nx, ny, nz = 96, 32, 32
     mean, box = workloads.turbine_row_inflow(ny=ny, nz=nz, hub_height=16.0, lt=32)
     rot = workloads.make_rotor(hub=(24.0, 15.5, 15.5), radius=6.0, n_blades=3, n_points=8,
                                tsr=7.0, u_ref=0.05)
-    sim = Lbm(nx, ny, nz, omega=1.9, storage=storage, bc_x="inout", bc_z=("noslip", "freeslip"))
+    sim = Lbm(nx, ny, nz, omega=1.9, storage=storage, closure=closure, bc_x="inout",
+              bc_z=("noslip", "freeslip"))
+    kw = {}
+    if closure == "mlp":
+        kw = {"closure": oracle.CLOSURE_MLP, "mlp_emulate_bf16": True}
     ref = oracle.Grid(nx, ny, nz, omega=1.9, bc_x=oracle.INOUT, bc_zlo=oracle.NOSLIP,
-                      bc_zhi=oracle.FREESLIP)
+                      bc_zhi=oracle.FREESLIP, **kw)
+    if closure == "mlp":
+        blob = _closure_blob()
+        sim.set_closure_weights(blob)
+        ref.set_mlp(blob)
     u0 = np.broadcast_to(mean[:, :, :, None], (3, nz, ny, nx)).copy()
     rho0 = np.ones((nz, ny, nx))
     sim.init_fields(rho0, u0)
@@ -137,7 +156,7 @@ def test_turbine_row_analogue_sheared_turbulent_inflow(storage, tol):
         sim.step(1)
         lg = sim.rotor_loads(0)
         lr = ref.rotor_loads(0)
-        assert np.abs(lg - lr).max() <= 2e-5 * np.abs(lr).max(), t
+        assert np.abs(lg - lr).max() <= ltol * np.abs(lr).max(), t
     err = np.abs(sim.pops() - ref.get_pops()).max()
-    print(f"turbine-row analogue ({storage}): max population error {err:.2e}")
+    print(f"turbine-row analogue ({storage}, closure {closure}): max population error {err:.2e}")
     assert err <= tol
