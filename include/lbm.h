@@ -78,6 +78,11 @@ typedef struct {
     double body_force[3];  /* uniform body force per cell */
     int check_every;       /* FP64 mass/NaN check period in steps; 0 = off */
     void *stream;          /* hipStream_t, or NULL */
+    int general_path;      /* 0: the library picks the stream-collide path
+                              (32-bit-offset fast path with per-lane
+                              inflow/outflow rules where offsets fit); 1: the
+                              64-bit general boundary path on every cell, for
+                              validation. Results agree to rounding. */
 } lbm_config;
 
 /* Create a context (validates cfg; no device memory is touched yet). */

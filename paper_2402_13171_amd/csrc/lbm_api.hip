@@ -133,7 +133,7 @@ bool general_bc(const lbm_ctx *c) {
            c->P * c->esize >= ((size_t)1 << 32);
 }
 static int sc_mode(const lbm_ctx *c) {
-    if (c->P * c->esize >= ((size_t)1 << 32)) return SC_GENERAL;
+    if (c->cfg.general_path || c->P * c->esize >= ((size_t)1 << 32)) return SC_GENERAL;
     return general_bc(c) ? SC_SPLIT : SC_FAST;
 }
 

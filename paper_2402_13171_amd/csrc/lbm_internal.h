@@ -84,9 +84,10 @@ constexpr int PT_STRIDE = 10;
 
 // Kernel launchers (defined in the .hip files).
 // mode: SC_FAST (periodic box, 32-bit offsets), SC_GENERAL (boundary rules
-// everywhere), SC_SPLIT (boundary rules, 32-bit offsets valid: odd steps run
-// the fast path, with the x inflow/outflow rules applied per lane, on all
-// cells off the z walls, and the general path on the wall planes)
+// everywhere), SC_SPLIT (boundary rules, 32-bit offsets valid: the fast path
+// with the x inflow/outflow rules applied per lane, on all cells in even
+// steps and on all cells off the z walls in odd steps, whose wall planes take
+// the general path)
 enum { SC_FAST = 0, SC_GENERAL = 1, SC_SPLIT = 2 };
 int launch_stream_collide(int storage, int parity, int closure, int mode, bool force,
                           bool general_rates, const Geo &g, const Physics &ph, hipStream_t s);

@@ -152,8 +152,9 @@ __device__ __forceinline__ void open_x_sources(const Geo &g, int x, int y, int z
 // lane of the wave: there it computes on (x, y, z) (a valid neighbour cell)
 // and stores nothing. mlp_lds: the workgroup's LDS copy of the network, its
 // DMA started by the caller (mlp_stage_lds).
-// XO (odd fast path only): x inflow/outflow rules per lane; the reads of the
-// x = 0 and x = nx-1 lanes from outside the box are replaced by the inlet
+// XO (fast path): x inflow/outflow rules per lane. Even steps: the x = nx-1
+// lanes also write the outflow ghost plane. Odd steps: the reads of the x = 0
+// and x = nx-1 lanes from outside the box are replaced by the inlet
 // equilibrium and the ghost plane, their pushes out of the box dropped, and
 // the slots no fluid cell pushes filled (odd_boundary_extras).
 template <typename T, int PAR, int CL, bool BCG, bool FRC, bool GR, bool XO = false>
@@ -217,7 +218,7 @@ __device__ __forceinline__ void cell_update(const Geo &g, const Physics &ph, int
     if (PAR == 0) {
         if (BCG) Unroll<T, 0>::write_swap_local(g, cell, o);
         else Unroll32<T, 0>::write_swap_local(gw, boff, o);
-        if (BCG && g.bc_x == BC_INOUT && x == g.nx - 1) {
+        if ((BCG || XO) && g.bc_x == BC_INOUT && x == g.nx - 1) {
             T *G = (T *)g.ghost;
 #pragma unroll
             for (int J = 0; J < 27; J += 3)
@@ -290,9 +291,20 @@ static void launch_sc(int mode, bool frc, bool gr, const Geo &g, const Physics &
     if (gr) {
         if (frc) k_stream_collide<T, PAR, CL, true, true, true><<<grd, blk, 0, s>>>(g, ph, gx, gy, total, twl);
         else k_stream_collide<T, PAR, CL, true, false, true><<<grd, blk, 0, s>>>(g, ph, gx, gy, total, twl);
-    } else if (mode == SC_GENERAL || (mode == SC_SPLIT && PAR == 0)) {
+    } else if (mode == SC_GENERAL) {
         if (frc) k_stream_collide<T, PAR, CL, true, true, false><<<grd, blk, 0, s>>>(g, ph, gx, gy, total, twl);
         else k_stream_collide<T, PAR, CL, true, false, false><<<grd, blk, 0, s>>>(g, ph, gx, gy, total, twl);
+    } else if (mode == SC_SPLIT && PAR == 0) {
+        // even step of an open domain: cell-local, the z walls play no part;
+        // only the x = nx-1 lanes add the outflow ghost plane
+        const bool xo = g.bc_x == BC_INOUT;
+        if (frc) {
+            if (xo) k_stream_collide<T, PAR, CL, false, true, false, true><<<grd, blk, 0, s>>>(g, ph, gx, gy, total, twl);
+            else k_stream_collide<T, PAR, CL, false, true, false><<<grd, blk, 0, s>>>(g, ph, gx, gy, total, twl);
+        } else {
+            if (xo) k_stream_collide<T, PAR, CL, false, false, false, true><<<grd, blk, 0, s>>>(g, ph, gx, gy, total, twl);
+            else k_stream_collide<T, PAR, CL, false, false, false><<<grd, blk, 0, s>>>(g, ph, gx, gy, total, twl);
+        }
     } else if (mode == SC_FAST) {
         if (frc) k_stream_collide<T, PAR, CL, false, true, false><<<grd, blk, 0, s>>>(g, ph, gx, gy, total, twl);
         else k_stream_collide<T, PAR, CL, false, false, false><<<grd, blk, 0, s>>>(g, ph, gx, gy, total, twl);

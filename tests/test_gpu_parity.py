@@ -25,10 +25,10 @@ def rel_vel_err(u, ref):
 
 
 def make_pair(nx, ny, nz, omega=1.9, storage="f32", closure="none", cs=0.1, bc_x="periodic",
-              bc_z=("periodic", "periodic"), u_in=(0, 0, 0), body_force=(0, 0, 0)):
+              bc_z=("periodic", "periodic"), u_in=(0, 0, 0), body_force=(0, 0, 0), general_path=False):
     from paper_2402_13171_amd.lbm import Lbm
     sim = Lbm(nx, ny, nz, omega=omega, storage=storage, closure=closure, cs_smag=cs,
-              bc_x=bc_x, bc_z=bc_z, u_in=u_in, body_force=body_force)
+              bc_x=bc_x, bc_z=bc_z, u_in=u_in, body_force=body_force, general_path=general_path)
     ref = oracle.Grid(nx, ny, nz, omega=omega, closure=oracle.CLOSURE_SMAG if closure == "smag" else 0,
                       cs=cs, bc_x=BCMAP[bc_x], bc_zlo=BCMAP[bc_z[0]], bc_zhi=BCMAP[bc_z[1]],
                       u_in=u_in, body_force=body_force)
@@ -94,10 +94,14 @@ def test_ragged_periodic_box_populations(steps):
     dict(bc_x="inout", bc_z=("freeslip", "freeslip"), u_in=(0.05, -0.01, 0.0)),
 ])
 @pytest.mark.parametrize("steps", [5, 6])
-def test_boundaries_match_oracle(case, steps):
+@pytest.mark.parametrize("general_path", [False, True], ids=["auto", "general"])
+def test_boundaries_match_oracle(case, steps, general_path):
+    """Open and walled boxes against the oracle, on the path the library picks
+    (fast path with per-lane inflow/outflow rules, wall planes on the general
+    path) and with the general 64-bit boundary path forced on every cell."""
     _need_gpu()
     nx, ny, nz = 20, 12, 10
-    sim, ref = make_pair(nx, ny, nz, omega=1.6, **case)
+    sim, ref = make_pair(nx, ny, nz, omega=1.6, general_path=general_path, **case)
     rho, u = random_field(nx, ny, nz, seed=3 + steps)
     sim.init_fields(rho, u)
     ref.init_fields(rho, u)
