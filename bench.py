@@ -31,6 +31,20 @@ def time_variant(n, rho, u, storage, closure, steps, warmup, blob=None):
     sim = Lbm(n, n, n, omega=1.9, storage=storage, closure=closure, cs_smag=0.1)
     if blob is not None:
         sim.set_closure_weights(blob)
+    # the access pattern alone (same buffers, tiles and addressing, no
+    # collision): the achievable ceiling of this kernel's memory traffic
+    probe_passes = 10
+    for par in (0, 1):
+        sim.pattern_probe(par)
+    torch.cuda.synchronize()
+    p0 = torch.cuda.Event(enable_timing=True)
+    p1 = torch.cuda.Event(enable_timing=True)
+    p0.record(sim.stream)
+    for k in range(probe_passes):
+        sim.pattern_probe(k % 2)
+    p1.record(sim.stream)
+    torch.cuda.synchronize()
+    probe_ms = p0.elapsed_time(p1) / probe_passes
     sim.init_fields(rho, u)
     sim.step(warmup)
     torch.cuda.synchronize()
@@ -48,7 +62,8 @@ def time_variant(n, rho, u, storage, closure, steps, warmup, blob=None):
     del sim
     torch.cuda.empty_cache()
     mlups = n ** 3 * steps / (ms * 1e-3) / 1e6
-    return {"mlups": mlups, "ms_per_step": ms / steps, "wall_s": wall, "mass": m, "ke": ke}
+    return {"mlups": mlups, "ms_per_step": ms / steps, "wall_s": wall, "mass": m, "ke": ke,
+            "pattern_ms": probe_ms}
 
 
 def closure_weights():
@@ -176,10 +191,12 @@ def main():
         nb = roofline.bytes_per_lup(s_bytes)
         bw = roofline.achieved_bandwidth(r["mlups"] * 1e6, nb)
         r.update({"bytes_per_lup": nb, "achieved_GBps": bw / 1e9,
-                  "hbm_frac": bw / roofline.HBM_PEAK_BPS})
+                  "hbm_frac": bw / roofline.HBM_PEAK_BPS,
+                  "pattern_GBps": nb * n ** 3 / (r["pattern_ms"] * 1e-3) / 1e9})
         results[v] = r
         log(f"bench: {v}: {r['mlups']:.0f} MLUPS, {r['ms_per_step']:.3f} ms/step, "
-            f"{bw / 1e9:.0f} GB/s algorithmic ({100 * bw / roofline.HBM_PEAK_BPS:.1f}% of 8 TB/s)")
+            f"{bw / 1e9:.0f} GB/s algorithmic ({100 * bw / roofline.HBM_PEAK_BPS:.1f}% of 8 TB/s; "
+            f"access-pattern probe {r['pattern_GBps']:.0f} GB/s)")
 
     base = results.get("f32") or next(iter(results.values()))
     cpu = None
@@ -214,6 +231,8 @@ def main():
                      "kernel": "k_stream_collide", "bytes_per_lup": nb,
                      "bytes_per_launch": nb * n ** 3},
         "cpu_baseline": cpu,
+        "pattern_probe": {"GBps": round(base["pattern_GBps"], 1), "ms_per_pass": round(base["pattern_ms"], 4),
+                          "kernel_frac_of_pattern": round(base["achieved_GBps"] / base["pattern_GBps"], 4)},
         "copy_probe": {"GBps": round(cbw["GBps"], 1), "bytes": cbw["bytes"],
                        "frac_of_peak": round(cbw["GBps"] * 1e9 / roofline.HBM_PEAK_BPS, 4),
                        "kernel_frac_of_copy": round(base["achieved_GBps"] / cbw["GBps"], 4)},
@@ -222,7 +241,9 @@ def main():
                          "achieved_GBps": round(v["achieved_GBps"], 1),
                          "hbm_frac": round(v["hbm_frac"], 4), "bytes_per_lup": v["bytes_per_lup"],
                          "ratio_vs_f32": round(v["mlups"] / base["mlups"], 3),
-                         "traffic": measured.get(k)}
+                         "traffic": measured.get(k),
+                         "pattern_probe_GBps": round(v["pattern_GBps"], 1),
+                         "frac_of_pattern_probe": round(v["achieved_GBps"] / v["pattern_GBps"], 4)}
                      for k, v in results.items()},
     }
     print(json.dumps(out), flush=True)

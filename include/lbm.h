@@ -231,6 +231,15 @@ int lbm_set_state(lbm_ctx *ctx, const void *host_buf, size_t bytes);
  * traffic counters against a kernel of known traffic. */
 int lbm_copy_probe(const void *d_src, void *d_dst, size_t bytes, void *stream);
 
+/* Access-pattern probe (measurement, Sec. 4.3's roofline): enqueue on the
+ * context's stream one pass of the stream-collide kernel's memory traffic
+ * for the given AA parity (0: read and write the own cell's 27 slots; 1: the
+ * neighbours' slots, periodic wrap) with the same tiling and addressing and
+ * no collision. Moves 27 * 2 * sizeof(storage) bytes per cell. The
+ * populations are left permuted: initialise again before stepping. Needs the
+ * 32-bit-offset layout (one population plane below 4 GiB). */
+int lbm_pattern_probe(lbm_ctx *ctx, int parity);
+
 const char *lbm_strerror(int code);
 const char *lbm_last_error(const lbm_ctx *ctx);
 

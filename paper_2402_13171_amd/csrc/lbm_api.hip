@@ -662,6 +662,16 @@ int lbm_rotor_loads(lbm_ctx *c, int id, double out[3], double *pt_force) {
     return LBM_OK;
 }
 
+int lbm_pattern_probe(lbm_ctx *c, int parity) {
+    int rc = ready(c);
+    if (rc) return rc;
+    if (parity != 0 && parity != 1) return fail(c, LBM_EINVAL, "parity must be 0 or 1");
+    if (c->P * c->esize >= ((size_t)1 << 32)) return fail(c, LBM_EINVAL, "probe needs 32-bit plane offsets");
+    if (launch_pattern_probe((int)c->cfg.storage, parity, geo_of(c), c->stream))
+        return fail(c, LBM_EHIP, "probe launch failed");
+    return LBM_OK;
+}
+
 int lbm_global_moments(lbm_ctx *c, double *mass, double mom[3], double *ke) {
     int rc = ready(c);
     if (rc) return rc;

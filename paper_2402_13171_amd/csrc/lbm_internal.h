@@ -92,6 +92,7 @@ enum { SC_FAST = 0, SC_GENERAL = 1, SC_SPLIT = 2 };
 int launch_stream_collide(int storage, int parity, int closure, int mode, bool force,
                           bool general_rates, const Geo &g, const Physics &ph, hipStream_t s);
 int launch_init_tgv(int storage, const Geo &g, double u0, double k, double rho0, hipStream_t s);
+int launch_pattern_probe(int storage, int parity, const Geo &g, hipStream_t s);
 int launch_init_eq(int storage, const Geo &g, const double *rho, const double *u, size_t cell0,
                    size_t ncell, hipStream_t s);
 int launch_fields(int storage, int parity, const Geo &g, const Physics &ph, double *rho, double *u,

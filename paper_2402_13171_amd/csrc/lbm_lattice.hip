@@ -280,6 +280,50 @@ __global__ __launch_bounds__(256) void k_stream_collide_walls(Geo g, Physics ph,
     cell_update<T, 1, CL, true, FRC, false>(g, ph, x, y, z, valid, mlp_lds);
 }
 
+// Pure-memory twin of the periodic fast path: the same tiles, tile order,
+// 32-bit offsets and AA access pattern of one step, no collision (each value
+// goes back to the slot the collision would write, so the store keeps its
+// content up to a permutation). Its rate is the achievable-bandwidth ceiling
+// of the stream-collide access pattern.
+template <typename T, int PAR>
+__global__ __launch_bounds__(256) void k_pattern_probe(Geo g, unsigned gx, unsigned gy, unsigned total,
+                                                       unsigned tw_log2) {
+    const unsigned tile = xcd_tile(blockIdx.x, total);
+    const unsigned tw = 1u << tw_log2, th = 256u >> tw_log2;
+    const int x = (int)((tile % gx) * tw + (threadIdx.x & (tw - 1)));
+    const int y = (int)(((tile / gx) % gy) * th + (threadIdx.x >> tw_log2));
+    const int z = (int)(tile / (gx * gy));
+    if (x >= g.nx || y >= g.ny) return;
+    float d[27];
+    if (PAR == 0) {
+        const uint32_t boff = (uint32_t)cidx(g, x, y, z) * (uint32_t)sizeof(T);
+        Unroll32<T, 0>::read_natural(g, boff, d);
+        Unroll32<T, 0>::write_swap_local(g, boff, d);
+    } else {
+        uint32_t xs[3], rows[9];
+        periodic_offsets(g, x, y, z, xs, rows);
+        Unroll32<T, 0>::read_periodic(g, xs, rows, d);
+        Unroll32<T, 0>::write_periodic(g, xs, rows, d);
+    }
+}
+
+int launch_pattern_probe(int storage, int parity, const Geo &g, hipStream_t s) {
+    const unsigned twl = g.nx >= 256 ? 8u : (g.nx >= 128 ? 7u : 6u);
+    const unsigned tw = 1u << twl, th = 256u >> twl;
+    const unsigned gx = (g.nx + tw - 1) / tw, gy = (g.ny + th - 1) / th, total = gx * gy * (unsigned)g.nz;
+    const dim3 grd(total, 1, 1), blk(256, 1, 1);
+    switch (storage * 2 + parity) {
+        case 0: k_pattern_probe<float, 0><<<grd, blk, 0, s>>>(g, gx, gy, total, twl); break;
+        case 1: k_pattern_probe<float, 1><<<grd, blk, 0, s>>>(g, gx, gy, total, twl); break;
+        case 2: k_pattern_probe<__half, 0><<<grd, blk, 0, s>>>(g, gx, gy, total, twl); break;
+        case 3: k_pattern_probe<__half, 1><<<grd, blk, 0, s>>>(g, gx, gy, total, twl); break;
+        case 4: k_pattern_probe<bf16_t, 0><<<grd, blk, 0, s>>>(g, gx, gy, total, twl); break;
+        case 5: k_pattern_probe<bf16_t, 1><<<grd, blk, 0, s>>>(g, gx, gy, total, twl); break;
+        default: return -1;
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
 // ------------------------------------------------------------ dispatch
 template <typename T, int PAR, int CL>
 static void launch_sc(int mode, bool frc, bool gr, const Geo &g, const Physics &ph, hipStream_t s) {

@@ -25,7 +25,7 @@ EXPORTS = [
     "lbm_init_fields", "lbm_set_rotor", "lbm_set_inflow", "lbm_step", "lbm_get_fields", "lbm_rotor_loads",
     "lbm_global_moments", "lbm_get_pops", "lbm_sample_pops", "lbm_get_filtered", "lbm_time", "lbm_set_force_field",
     "lbm_set_closure_weights", "lbm_state_bytes", "lbm_get_state", "lbm_set_state",
-    "lbm_strerror", "lbm_last_error", "lbm_copy_probe",
+    "lbm_strerror", "lbm_last_error", "lbm_copy_probe", "lbm_pattern_probe",
     "lbm_mlp_create", "lbm_mlp_destroy", "lbm_mlp_set_params", "lbm_mlp_get_params",
     "lbm_mlp_forward", "lbm_mlp_loss_grad", "lbm_mlp_adam_step", "lbm_mlp_take_loss",
     "lbm_mlp_last_error",
@@ -122,6 +122,8 @@ def lib():
     L.lbm_mlp_last_error.restype = C.c_char_p
     L.lbm_copy_probe.argtypes = [vp, vp, sz, vp]
     L.lbm_copy_probe.restype = C.c_int
+    L.lbm_pattern_probe.argtypes = [vp, C.c_int]
+    L.lbm_pattern_probe.restype = C.c_int
     L.lbm_strerror.argtypes = [i]
     L.lbm_strerror.restype = C.c_char_p
     L.lbm_last_error.argtypes = [vp]
@@ -243,6 +245,11 @@ class Lbm:
             box = _f64(box)
             lt = box.shape[1]
             self._check(lib().lbm_set_inflow(self._ctx, _p(mean), _p(box.reshape(-1)), lt, float(advect)))
+
+    def pattern_probe(self, parity):
+        """One pass of the stream-collide memory traffic without the
+        collision (leaves the populations permuted: initialise afterwards)."""
+        self._check(lib().lbm_pattern_probe(self._ctx, int(parity)))
 
     def step(self, n=1):
         self._check(lib().lbm_step(self._ctx, int(n)))

@@ -161,6 +161,27 @@ def test_checkpoint_roundtrip_is_bitwise():
     assert np.array_equal(b.pops(), f1)
 
 
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_pattern_probe_is_an_involution(storage):
+    """The access-pattern probe moves every value to the slot the collision
+    would write; two passes of one parity put every value back (even: swap of
+    slots i and 26-i; odd: slot 26-i at x-c_i <-> slot i at x+c_i), over a
+    ragged box whose tiles overhang in x and y."""
+    _need_gpu()
+    from paper_2402_13171_amd.lbm import Lbm
+    nx, ny, nz = 70, 9, 5
+    sim = Lbm(nx, ny, nz, omega=1.7, storage=storage)
+    rho, u = random_field(nx, ny, nz, seed=12)
+    sim.init_fields(rho, u)
+    s0 = np.asarray(sim.get_state()).copy()
+    for parity in (0, 1):
+        sim.pattern_probe(parity)
+        s1 = np.asarray(sim.get_state()).copy()
+        assert not np.array_equal(s1, s0)
+        sim.pattern_probe(parity)
+        assert np.array_equal(np.asarray(sim.get_state()), s0), parity
+
+
 def test_invalid_state_is_reported():
     """The check fires (LBM_EUNSTABLE) for a state that is no longer valid,
     planted from the host: uniform flow at |u| = 2 lattice units is an exact
