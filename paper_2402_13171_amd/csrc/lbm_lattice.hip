@@ -78,14 +78,21 @@ __device__ __forceinline__ void odd_boundary_extras(const Geo &g, int x, int y, 
 }
 
 // Workgroups are dealt round-robin to the 8 XCDs (each with its own L2).
-// Renumber them so that XCD j works through one contiguous range of tiles:
-// tiles adjacent in x (whose odd-step reads share cache lines at the tile
-// edge) and in y then land on the same L2. Bijective for any tile count.
+// Renumber them so that XCD j works through chunks of XCD_CHUNK consecutive
+// tiles (chunks j, j+8, j+16, ...): tiles adjacent in x, whose odd-step reads
+// share cache lines at the tile edge, land on the same L2, while the eight
+// XCDs' current chunks stay adjacent, so that the chip as a whole streams one
+// contiguous window of every plane. (Handing each XCD one contiguous eighth
+// of the tiles instead, eight windows far apart in every plane, measured up
+// to 7% slower for 16-bit storage and about 2% for FP32.) Tiles past the last
+// whole group of 8 chunks keep their own number. Bijective for any count.
+constexpr unsigned XCD_CHUNK = 1024;
 __device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned total) {
     constexpr unsigned NX = 8;
-    const unsigned q = total / NX, r = total % NX;
+    const unsigned full = total - total % (NX * XCD_CHUNK);
+    if (b >= full) return b;
     const unsigned xcd = b % NX, local = b / NX;
-    return xcd < r ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
+    return ((local / XCD_CHUNK) * NX + xcd) * XCD_CHUNK + local % XCD_CHUNK;
 }
 
 // One workgroup of 256 threads = one tile of tw (x) by 256/tw (y) cells in one
