@@ -18,7 +18,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
-_SRC = ["orc_lattice.c", "orc_mlp.c", "orc_solver.c", "orc_alm.c"]
+_SRC = ["orc_lattice.c", "orc_mlp.c", "orc_solver.c", "orc_alm.c", "orc_turbine.c"]
 
 PERIODIC, INOUT, NOSLIP, FREESLIP = 0, 1, 2, 3
 CLOSURE_NONE, CLOSURE_SMAG, CLOSURE_MLP = 0, 1, 2
@@ -72,6 +72,30 @@ class RotorDesc(C.Structure):
 KERNEL_GAUSS, KERNEL_ROMA3 = 0, 1
 
 
+class NodeDesc(C.Structure):
+    _fields_ = [("parent", C.c_int), ("kind", C.c_int), ("force", C.c_int),
+                ("n_points", C.c_int), ("n_azimuth", C.c_int), ("tip_loss", C.c_int),
+                ("pos", C.c_double * 3), ("rot", C.c_double * 9), ("axis", C.c_double * 3),
+                ("omega", C.c_double), ("angle0", C.c_double),
+                ("amp", C.c_double), ("freq", C.c_double), ("phase", C.c_double),
+                ("disp", C.c_double * 3), ("dir", C.c_double * 3), ("normal", C.c_double * 3),
+                ("coef", C.c_double), ("pitch_deg", C.c_double),
+                ("s", C.POINTER(C.c_double)), ("width", C.POINTER(C.c_double)),
+                ("chord", C.POINTER(C.c_double)), ("twist", C.POINTER(C.c_double))]
+
+
+class TurbineDesc(C.Structure):
+    _fields_ = [("n_nodes", C.c_int), ("nodes", C.POINTER(NodeDesc)),
+                ("kernel", C.c_int), ("eps", C.c_double),
+                ("n_blades", C.c_int), ("radius", C.c_double),
+                ("n_polar", C.c_int), ("alpha_deg", C.POINTER(C.c_double)),
+                ("cl", C.POINTER(C.c_double)), ("cd", C.POINTER(C.c_double))]
+
+
+NODE_KIND = {"frame": 0, "line": 1, "disk": 2}
+FORCE_KIND = {"none": 0, "blade": 1, "drag": 2}
+
+
 _D = C.POINTER(C.c_double)
 
 
@@ -117,6 +141,10 @@ def _declare(L):
         "orc_spread_point_roma": (v, [C.c_void_p, _D, _D, _D]),
         "orc_roma_phi": (C.c_double, [C.c_double]),
         "orc_tip_loss": (C.c_double, [C.c_int, C.c_double, C.c_double, C.c_double]),
+        "orc_set_turbine": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(TurbineDesc)]),
+        "orc_turbine_npoints": (C.c_int, [C.POINTER(TurbineDesc)]),
+        "orc_turbine_kinematics": (C.c_int, [C.POINTER(TurbineDesc), C.c_double, _D, _D, _D]),
+        "orc_turbine_loads": (v, [C.c_void_p, C.c_int, _D, _D]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -242,6 +270,64 @@ def inflow_plane(mean, box, advect, t):
     return mean + (1.0 - f) * box[:, s0] + f * box[:, s1]
 
 
+def _turbine_desc(turbine, keep):
+    """ctypes description of a turbine dict (workloads.turbines format)."""
+    nodes = turbine["nodes"]
+    arr = (NodeDesc * len(nodes))()
+    for k, nd in enumerate(nodes):
+        d = arr[k]
+        d.parent = nd.get("parent", -1)
+        d.kind = NODE_KIND[nd.get("kind", "frame")]
+        d.force = FORCE_KIND[nd.get("force", "none")]
+        d.n_azimuth = nd.get("n_azimuth", 0)
+        d.tip_loss = int(bool(nd.get("tip_loss", False)))
+        rot = np.asarray(nd.get("rot", np.eye(3)), dtype=np.float64).reshape(9)
+        for a in range(9):
+            d.rot[a] = rot[a]
+        for name in ("pos", "axis", "disp", "dir", "normal"):
+            vec = nd.get(name, (0.0, 0.0, 0.0) if name != "axis" else (1.0, 0.0, 0.0))
+            for a in range(3):
+                getattr(d, name)[a] = vec[a]
+        for name in ("omega", "angle0", "amp", "freq", "phase", "coef", "pitch_deg"):
+            setattr(d, name, float(nd.get(name, 0.0)))
+        n = 0
+        for name in ("s", "width", "chord", "twist"):
+            if nd.get(name) is not None:
+                a = _f64(nd[name])
+                keep.append(a)
+                setattr(d, name, _p(a))
+                n = len(a)
+        d.n_points = n
+    keep.append(arr)
+    t = TurbineDesc()
+    t.n_nodes = len(nodes)
+    t.nodes = arr
+    t.kernel = {"gauss": KERNEL_GAUSS, "roma3": KERNEL_ROMA3}[turbine.get("kernel", "gauss")]
+    t.eps = float(turbine.get("eps", 2.0))
+    t.n_blades = int(turbine.get("n_blades", 0))
+    t.radius = float(turbine.get("radius", 0.0))
+    pol = turbine.get("polar")
+    if pol is not None:
+        pa = {k: _f64(pol[k]) for k in ("alpha_deg", "cl", "cd")}
+        keep += list(pa.values())
+        t.n_polar = len(pa["alpha_deg"])
+        t.alpha_deg, t.cl, t.cd = _p(pa["alpha_deg"]), _p(pa["cl"]), _p(pa["cd"])
+    return t
+
+
+def turbine_kinematics(turbine, t):
+    """Positions x[npts][3], velocities v[npts][3] and node frames
+    [n_nodes][15] (T row-major, origin, angular velocity) at time t."""
+    keep = []
+    d = _turbine_desc(turbine, keep)
+    n = lib().orc_turbine_npoints(C.byref(d))
+    x, v = np.zeros((n, 3)), np.zeros((n, 3))
+    fr = np.zeros((d.n_nodes, 15))
+    if lib().orc_turbine_kinematics(C.byref(d), float(t), _p(x), _p(v), _p(fr)) != 0:
+        raise ValueError("oracle: bad turbine")
+    return x, v, fr
+
+
 # ---------------------------------------------------------------- domain solver
 class Grid:
     """Two-array FP64 solver on an nx x ny x nz box (x fastest)."""
@@ -358,6 +444,24 @@ class Grid:
         pos = np.zeros((self._rotor_np[rid], 3))
         lib().orc_rotor_points(self._h, rid, _p(pos))
         return pos
+
+    def set_turbine(self, tid, turbine):
+        """turbine: dict as produced by workloads.turbines."""
+        keep = []
+        d = _turbine_desc(turbine, keep)
+        if lib().orc_set_turbine(self._h, tid, C.byref(d)) != 0:
+            raise ValueError("oracle: bad turbine")
+        self._keep += keep
+        self._turb = getattr(self, "_turb", {})
+        self._turb[tid] = (d.n_nodes, lib().orc_turbine_npoints(C.byref(d)))
+
+    def turbine_loads(self, tid):
+        """(node_loads[n_nodes][7]: F, M about the node origin, P;
+        points[npts][9]: x, v, F) of the last step."""
+        nn, npts = self._turb[tid]
+        nl, pts = np.zeros((nn, 7)), np.zeros((npts, 9))
+        lib().orc_turbine_loads(self._h, tid, _p(nl), _p(pts))
+        return nl, pts
 
     def trilinear(self, field, x):
         field = _f64(field)

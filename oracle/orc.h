@@ -121,6 +121,53 @@ void orc_spread_point_roma(const orc_grid *g, const double xp[3],
                            const double Fp[3], double *F);
 double orc_tip_loss(int n_blades, double radius, double r, double phi_rad);
 
+/* ---- turbine topology tree (orc_turbine.c) ---- */
+#define ORC_MAX_NODES 32
+enum { ORC_NODE_FRAME = 0, ORC_NODE_LINE = 1, ORC_NODE_DISK = 2 };
+enum { ORC_FORCE_NONE = 0, ORC_FORCE_BLADE = 1, ORC_FORCE_DRAG = 2 };
+typedef struct {
+    int parent;            /* parent index (< own index), -1 for a root */
+    int kind;              /* ORC_NODE_* */
+    int force;             /* ORC_FORCE_* */
+    int n_points;          /* line points / disk rings */
+    int n_azimuth;         /* disk points per ring */
+    int tip_loss;
+    double pos[3];         /* p_r, parent frame */
+    double rot[9];         /* T_r, row-major */
+    double axis[3];        /* rotation axis of R, frame T_p T_r */
+    double omega, angle0;
+    double amp, freq, phase;
+    double disp[3];
+    double dir[3];         /* line direction, node frame */
+    double normal[3];      /* blade-element normal, node frame */
+    double coef;           /* drag / thrust coefficient */
+    double pitch_deg;
+    const double *s, *width, *chord, *twist;
+} orc_node;
+typedef struct {
+    int n_nodes;
+    const orc_node *nodes;
+    int kernel;
+    double eps;
+    int n_blades;
+    double radius;
+    int n_polar;
+    const double *alpha_deg, *cl, *cd;
+} orc_turbine_desc;
+
+int  orc_set_turbine(orc_grid *g, int id, const orc_turbine_desc *d);
+int  orc_turbine_npoints(const orc_turbine_desc *d);
+/* positions x[npts][3] and velocities v[npts][3] of every point at time t,
+ * and per node (nullable) frames[n_nodes][15]: T[9], origin[3], angular
+ * velocity[3]; no grid involved */
+int  orc_turbine_kinematics(const orc_turbine_desc *d, double t, double *x,
+                            double *v, double *frames);
+/* per node [n_nodes][7]: F[3], moment about the node origin[3], power;
+ * per point [npts][9]: x, v, F (both nullable) */
+void orc_turbine_loads(const orc_grid *g, int id, double *node_loads,
+                       double *pts);
+void orc__turbines_step(orc_grid *g, const double *fld);
+
 /* internal: the ALM sub-steps of one time step, called by orc_step */
 void orc_alm_step(orc_grid *g);
 

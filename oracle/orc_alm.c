@@ -46,6 +46,8 @@ double *orc__pops(orc_grid *g);
 double *orc__frot(orc_grid *g);
 double *orc__fext(orc_grid *g);
 void **orc__rotors(orc_grid *g);
+void **orc__turbines(orc_grid *g);
+void orc__free_turbine(void *t);
 const orc_params *orc__params(const orc_grid *g);
 const double *orc__cpops(const orc_grid *g);
 const double *orc__cfrot(const orc_grid *g);
@@ -84,6 +86,10 @@ int orc_set_rotor(orc_grid *g, int id, const orc_rotor_desc *d)
         return -1;
     void **rs = orc__rotors(g);
     orc__free_rotor(rs[id]);
+    /* a slot holds a rotor or a turbine */
+    void **ts = orc__turbines(g);
+    orc__free_turbine(ts[id]);
+    ts[id] = NULL;
     rotor_t *r = (rotor_t *)calloc(1, sizeof(rotor_t));
     r->d = *d;
     int np = d->n_points, npts = d->n_blades * d->n_points;
@@ -356,6 +362,7 @@ void orc_alm_step(orc_grid *g)
         R->loads[1] = Q;
         R->loads[2] = Q * d->omega_rot;
     }
+    orc__turbines_step(g, fld);
     free(fld);
 }
 

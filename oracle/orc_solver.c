@@ -35,6 +35,7 @@ struct orc_grid {
     int has_mlp;
     long t;
     void *rotors[ORC_MAX_ROTORS];
+    void *turbines[ORC_MAX_ROTORS];
 };
 
 /* accessors shared with orc_alm.c */
@@ -47,7 +48,10 @@ const double *orc__cpops(const orc_grid *g) { return g->f; }
 const double *orc__cfrot(const orc_grid *g) { return g->frot; }
 const double *orc__cfext(const orc_grid *g) { return g->fext; }
 void *const *orc__crotors(const orc_grid *g) { return g->rotors; }
+void **orc__turbines(orc_grid *g) { return g->turbines; }
+void *const *orc__cturbines(const orc_grid *g) { return g->turbines; }
 void orc__free_rotor(void *r);
+void orc__free_turbine(void *t);
 
 static inline size_t cell(const orc_grid *g, int x, int y, int z)
 {
@@ -87,8 +91,10 @@ void orc_destroy(orc_grid *g)
 {
     if (!g)
         return;
-    for (int r = 0; r < ORC_MAX_ROTORS; ++r)
+    for (int r = 0; r < ORC_MAX_ROTORS; ++r) {
         orc__free_rotor(g->rotors[r]);
+        orc__free_turbine(g->turbines[r]);
+    }
     free(g->f);
     free(g->ft);
     free(g->fext);
@@ -225,7 +231,7 @@ void orc_step(orc_grid *g, int nsteps)
     for (int s = 0; s < nsteps; ++s) {
         int any_rotor = 0;
         for (int r = 0; r < ORC_MAX_ROTORS; ++r)
-            any_rotor |= g->rotors[r] != NULL;
+            any_rotor |= g->rotors[r] != NULL || g->turbines[r] != NULL;
         if (any_rotor)
             orc_alm_step(g);
 
