@@ -161,6 +161,94 @@ int lbm_get_fields(lbm_ctx *ctx, double *rho, double *u);
  * force on each blade point, [n_blades*n_points][3]. Synchronises. */
 int lbm_rotor_loads(lbm_ctx *ctx, int rotor_id, double out[3], double *pt_force);
 
+/* ---- turbine topology tree (Sec. 3.3, Alg. 1 and Alg. 2) ----
+ * A turbine is a tree of components (tower, nacelle, hub, blades, disks),
+ * each placed and oriented relative to its parent. Nodes are given in an
+ * order where every parent precedes its children. At step t, node c with
+ * parent p gets the world orientation and origin
+ *   T_c = T_p T_r R(t),   o_c = o_p + T_p (pos + disp sin(freq t + phase)),
+ * T_p = identity and o_p = 0 for the root; R(t) is the rotation about the
+ * unit vector axis (in the frame T_p T_r) by the angle
+ *   angle0 + omega t + amp sin(freq t + phase)
+ * (omega: constant rotor or yaw rate; amp/freq/phase and disp: a prescribed
+ * oscillation such as a floating platform's pitch and surge). A point with
+ * node-frame offset q sits at x = o_c + T_c q and moves with the velocity
+ * that this motion implies (the sum over the node and its ancestors of each
+ * rotation rate times axis, crossed with the lever arm, plus the rates of
+ * the displacements). Discretisations (Alg. 2):
+ *   LBM_NODE_FRAME  no points (a joint: hub, nacelle frame, platform);
+ *   LBM_NODE_LINE   n_points points q_k = s[k] dir (a blade, a tower);
+ *   LBM_NODE_DISK   n_points rings of n_azimuth points, ring j at radius
+ *                   s[j] in the node's y-z plane, point k at angle
+ *                   2 pi k / n_azimuth from +y towards +z; the disk normal
+ *                   is the node's x axis; a point stands for the area
+ *                   2 pi s[j] width[j] / n_azimuth.
+ * Force models (force on the structure; the fluid receives its reaction,
+ * W = u - v is the sampled velocity relative to the moving point):
+ *   LBM_FORCE_BLADE (lines only) blade element as in lbm_set_rotor, in the
+ *     plane of e_n = T_c normal and e_t = e_n x e_s, e_s = T_c dir:
+ *     W_n = W.e_n, W_t = -W.e_t, angle of attack
+ *     atan2(W_n, W_t) - twist[k] - pitch_deg, force
+ *     1/2 rho (W_n^2 + W_t^2) chord[k] width[k] (C_L e_L + C_D e_D) in that
+ *     plane; tip_loss = 1 applies the Prandtl factor with the turbine's
+ *     n_blades and radius at r = s[k];
+ *   LBM_FORCE_DRAG on a line: cross-flow drag of a cylinder of diameter
+ *     chord[k] and length width[k], 1/2 rho coef chord[k] width[k] |W_p| W_p
+ *     with W_p = W - (W.e_s) e_s;
+ *   LBM_FORCE_DRAG on a disk: normal force 1/2 rho coef A |W.n| (W.n) n,
+ *     n the disk normal, A the point's area; with coef = C_T' (thrust
+ *     coefficient on the local normal velocity) this is the actuator disk.
+ *   LBM_FORCE_NONE: points that only sample (probes).
+ * Spreading as for rotors (kernel, eps). At most 32 nodes, depth 16, 512
+ * points per turbine. A turbine takes one of the 8 rotor slots (set_rotor
+ * and set_turbine replace whatever the slot held). The spreading box covers
+ * every point's reach over all times (from the rotation and oscillation
+ * amplitudes) and must lie inside the domain. All arrays are copied. */
+enum { LBM_NODE_FRAME = 0, LBM_NODE_LINE = 1, LBM_NODE_DISK = 2 };
+enum { LBM_FORCE_NONE = 0, LBM_FORCE_BLADE = 1, LBM_FORCE_DRAG = 2 };
+typedef struct {
+    int parent;            /* index of the parent node (smaller than own); -1: root */
+    int kind;              /* LBM_NODE_* */
+    int force;             /* LBM_FORCE_* */
+    int n_points;          /* LINE: points; DISK: rings */
+    int n_azimuth;         /* DISK: points per ring */
+    int tip_loss;          /* BLADE: 0 or 1 */
+    double pos[3];         /* origin relative to the parent's, parent frame */
+    double rot[9];         /* T_r, row-major, orthonormal with determinant +1 */
+    double axis[3];        /* unit rotation axis (need not be set if static) */
+    double omega, angle0;  /* rad/step, rad */
+    double amp, freq, phase;
+    double disp[3];        /* oscillating origin displacement, parent frame */
+    double dir[3];         /* LINE: unit direction, node frame */
+    double normal[3];      /* BLADE: unit vector normal to dir, node frame */
+    double coef;           /* DRAG: drag or thrust coefficient */
+    double pitch_deg;      /* BLADE */
+    const double *s;       /* [n_points] LINE distance along dir / DISK ring radius */
+    const double *width;   /* [n_points] LINE element length / DISK ring width */
+    const double *chord;   /* [n_points] BLADE chord / line DRAG diameter; NULL otherwise */
+    const double *twist;   /* [n_points] BLADE twist, degrees; NULL otherwise */
+} lbm_node;
+typedef struct {
+    int n_nodes;
+    const lbm_node *nodes;
+    int kernel;            /* LBM_KERNEL_GAUSS or LBM_KERNEL_ROMA3 */
+    double eps;            /* Gaussian width */
+    int n_blades;          /* tip-loss factor: blades and tip radius */
+    double radius;
+    int n_polar;           /* polars of every BLADE node (>= 2 if any) */
+    const double *alpha_deg, *cl, *cd;
+} lbm_turbine;
+int lbm_set_turbine(lbm_ctx *ctx, int turbine_id, const lbm_turbine *turbine);
+
+/* Loads of a turbine at the last step, per node (node_loads[n_nodes][7]:
+ * total force on the node's points F[3], moment about the node's origin
+ * sum (x - o_c) x F [3], power sum F.v) and, if pts is not NULL, per point
+ * (pts[n_points_total][9]: position x[3], velocity v[3], force F[3]; points
+ * in node order, rings before azimuth on disks). Synchronises. */
+int lbm_turbine_loads(lbm_ctx *ctx, int turbine_id, double *node_loads, double *pts);
+/* Number of points of the turbine in slot turbine_id (size of pts above). */
+int lbm_turbine_points(const lbm_ctx *ctx, int turbine_id, int *n_points_total);
+
 /* FP64 totals over the domain: mass sum rho, momentum sum rho u, kinetic
  * energy 1/2 sum rho |u|^2. Synchronises. */
 int lbm_global_moments(lbm_ctx *ctx, double *mass, double mom[3], double *kin_energy);

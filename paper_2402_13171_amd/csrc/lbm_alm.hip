@@ -47,12 +47,133 @@ __device__ __forceinline__ double tip_loss_factor(int B, double R, double r, dou
     return (2.0 / PI_D) * acos(exp(-0.5 * B * (R - r) / (r * s)));
 }
 
+// ------------------------------------------------------------ turbine tree
+// World pose of a node (Sec. 3.3, Alg. 2): composed from the root down,
+// T_c = T_p T_r R(theta), o_c = o_p + T_p p_r, with theta = angle0 + omega t
+// + amp sin(freq t + phase) about the node's axis and p_r = pos + disp
+// sin(freq t + phase); alongside, the angular velocity w_c = w_p + T_p T_r
+// (dtheta/dt) axis and the velocity of the origin v_c = v_p + w_p x (T_p p_r)
+// + T_p dp_r/dt, so that a point x of the node moves with v_c + w_c x (x - o_c).
+struct TreePose {
+    double T[9], o[3], w[3], vo[3];
+};
+
+__device__ __forceinline__ void m3mul(const double *A, const double *B, double *C) {
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) C[3 * i + j] = A[3 * i] * B[j] + A[3 * i + 1] * B[3 + j] + A[3 * i + 2] * B[6 + j];
+}
+__device__ __forceinline__ void m3vec(const double *A, const double *x, double *y) {
+    for (int i = 0; i < 3; ++i) y[i] = A[3 * i] * x[0] + A[3 * i + 1] * x[1] + A[3 * i + 2] * x[2];
+}
+__device__ __forceinline__ void cross3(const double *a, const double *b, double *c) {
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+__device__ __forceinline__ double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+__device__ void tree_pose(const NodeDev *nodes, int node, double t, TreePose &P) {
+    int chain[TREE_MAX_DEPTH];
+    int d = 0;
+    for (int k = node; k >= 0 && d < TREE_MAX_DEPTH; k = nodes[k].parent) chain[d++] = k;  // depth checked on the host
+    for (int a = 0; a < 9; ++a) P.T[a] = (a % 4 == 0) ? 1.0 : 0.0;
+    for (int a = 0; a < 3; ++a) P.o[a] = P.w[a] = P.vo[a] = 0.0;
+    for (int i = d - 1; i >= 0; --i) {
+        const NodeDev &N = nodes[chain[i]];
+        double sph, cph, st, ct;
+        sincos(N.freq * t + N.phase, &sph, &cph);
+        const double th = N.angle0 + N.omega * t + N.amp * sph;
+        const double dth = N.omega + N.amp * N.freq * cph;
+        sincos(th, &st, &ct);
+        const double *a = N.axis;
+        const double k1 = 1.0 - ct;
+        // rotation by th about the unit axis a (Rodrigues)
+        const double R[9] = {ct + k1 * a[0] * a[0],        k1 * a[0] * a[1] - st * a[2], k1 * a[0] * a[2] + st * a[1],
+                             k1 * a[1] * a[0] + st * a[2], ct + k1 * a[1] * a[1],        k1 * a[1] * a[2] - st * a[0],
+                             k1 * a[2] * a[0] - st * a[1], k1 * a[2] * a[1] + st * a[0], ct + k1 * a[2] * a[2]};
+        double TpTr[9], Tn[9], pr[3], dpr[3], Tpr[3], Tdpr[3], wa[3], wx[3];
+        m3mul(P.T, N.rot, TpTr);
+        m3mul(TpTr, R, Tn);
+        for (int c = 0; c < 3; ++c) {
+            pr[c] = N.pos[c] + N.disp[c] * sph;
+            dpr[c] = N.disp[c] * N.freq * cph;
+        }
+        m3vec(P.T, pr, Tpr);
+        m3vec(P.T, dpr, Tdpr);
+        m3vec(TpTr, N.axis, wa);
+        cross3(P.w, Tpr, wx);
+        for (int c = 0; c < 3; ++c) {
+            P.o[c] += Tpr[c];
+            P.vo[c] += wx[c] + Tdpr[c];
+            P.w[c] += dth * wa[c];
+        }
+        for (int c = 0; c < 9; ++c) P.T[c] = Tn[c];
+    }
+}
+
+// Position (and, with v != nullptr, velocity and the node pose) of point p
+// of slot R at time t: a rotor's blade element or a turbine point.
+__device__ __forceinline__ void slot_point(const RotorDev &R, int p, double t, double xp[3], double *v,
+                                           TreePose *pose, double *Tq) {
+    if (R.nodes) {
+        const TreePointDev &tp = R.tpts[p];
+        TreePose P;
+        tree_pose(R.nodes, tp.node, t, P);
+        double q[3] = {tp.q[0], tp.q[1], tp.q[2]}, tq[3];
+        m3vec(P.T, q, tq);
+        for (int a = 0; a < 3; ++a) xp[a] = P.o[a] + tq[a];
+        if (v) {
+            double wq[3];
+            cross3(P.w, tq, wq);
+            for (int a = 0; a < 3; ++a) {
+                v[a] = P.vo[a] + wq[a];
+                Tq[a] = tq[a];
+            }
+            *pose = P;
+        }
+    } else {
+        const int b = p / R.n_points, k = p % R.n_points;
+        const double th = R.azimuth0 + R.omega_rot * t + 2.0 * PI_D * b / R.n_blades;
+        const double rr = R.r[k];
+        xp[0] = R.hub[0];
+        xp[1] = R.hub[1] + rr * cos(th);
+        xp[2] = R.hub[2] + rr * sin(th);
+    }
+}
+
+// Blade-element force (Sec. 2.2) from the in-plane relative wind: W_n along
+// the rotor normal, W_t against the blade's motion; Fn, Ft along e_n, e_t.
+__device__ __forceinline__ void blade_element(const RotorDev &R, double rho, double wn, double wt, double chord,
+                                              double dl, double twist, double pitch, int tip_loss, double r,
+                                              double &Fn, double &Ft) {
+    double a = atan2(wn, wt) * (180.0 / PI_D) - twist - pitch;
+    // |phi| <= 180 and |twist + pitch| < 180: one correction wraps to [-180, 180)
+    if (a >= 180.0) a -= 360.0;
+    else if (a < -180.0) a += 360.0;
+    const double CL = polar_lookup(a, R, R.cl), CD = polar_lookup(a, R, R.cd);
+    const double w2 = wn * wn + wt * wt, wm = sqrt(w2);
+    const double q = 0.5 * rho * w2 * chord * dl;
+    Fn = 0.0;
+    Ft = 0.0;
+    if (wm > 0.0) {
+        Fn = q * (CL * wt + CD * wn) / wm;
+        Ft = q * (CL * wn - CD * wt) / wm;
+    }
+    if (tip_loss) {
+        const double Fl = tip_loss_factor(R.n_blades, R.radius, r, atan2(wn, wt));
+        Fn *= Fl;
+        Ft *= Fl;
+    }
+}
+
 // Points are processed in batches of 32: workgroup (b, r) handles points
-// 32b .. 32b+31 of rotor r. Its 256 threads first stage the density and
+// 32b .. 32b+31 of slot r. Its 256 threads first stage the density and
 // velocity of the 8 cells around each of the 32 points in LDS (thread ->
-// point, corner), then 32 threads interpolate and evaluate the blade
-// elements. Each workgroup leaves FP64 partial thrust and torque; the host
-// adds the partials in batch order when the loads are read.
+// point, corner), then 32 threads interpolate and evaluate the force model.
+// A rotor leaves FP64 partial thrust and torque per workgroup (the host adds
+// the partials in batch order when the loads are read); a turbine leaves
+// per point x, v, F and the moment (x - o_node) x F, which the host sums
+// per node.
 constexpr int ALM_BATCH = ALM_BLOCK / 8;
 static_assert(ALM_BATCH == ALM_BATCH_PTS, "batch size shared with the host-side load sum");
 constexpr int ALM_MAX_BATCHES = ALM_MAX_PTS / ALM_BATCH;
@@ -60,7 +181,7 @@ constexpr int ALM_MAX_BATCHES = ALM_MAX_PTS / ALM_BATCH;
 template <typename T, int PAR>
 __global__ __launch_bounds__(ALM_BLOCK) void k_alm_points(Geo g, Physics ph, RotorDev *rots, long t) {
     RotorDev &R = rots[blockIdx.y];
-    const int npts = R.n_blades * R.n_points;
+    const int npts = R.npts;
     const int base = blockIdx.x * ALM_BATCH;
     if (base >= npts) return;  // uniform across the workgroup
     __shared__ double s_corner[ALM_BLOCK][4];  // rho, u of one corner cell per work item
@@ -68,10 +189,8 @@ __global__ __launch_bounds__(ALM_BLOCK) void k_alm_points(Geo g, Physics ph, Rot
     {
         const int p = base + threadIdx.x / 8, corner = threadIdx.x % 8;
         if (p < npts) {
-            const int b = p / R.n_points, k = p % R.n_points;
-            const double th = R.azimuth0 + R.omega_rot * (double)t + 2.0 * PI_D * b / R.n_blades;
-            const double rr = R.r[k];
-            const double xp[3] = {R.hub[0], R.hub[1] + rr * cos(th), R.hub[2] + rr * sin(th)};
+            double xp[3];
+            slot_point(R, p, (double)t, xp, nullptr, nullptr, nullptr);
             const int dx = corner & 1, dy = (corner >> 1) & 1, dz = corner >> 2;
             const int cx = wrap_any((int)floor(xp[0]) + dx, g.nx);
             const int cy = wrap_any((int)floor(xp[1]) + dy, g.ny);
@@ -89,11 +208,9 @@ __global__ __launch_bounds__(ALM_BLOCK) void k_alm_points(Geo g, Physics ph, Rot
         double accT = 0.0, accQ = 0.0;
         const int p = base + threadIdx.x;
         if (p < npts) {
-            const int b = p / R.n_points, k = p % R.n_points;
-            const double th = R.azimuth0 + R.omega_rot * (double)t + 2.0 * PI_D * b / R.n_blades;
-            const double ct = cos(th), st = sin(th);
-            const double rr = R.r[k];
-            const double xp[3] = {R.hub[0], R.hub[1] + rr * ct, R.hub[2] + rr * st};
+            double xp[3], vp[3] = {0, 0, 0}, Tq[3] = {0, 0, 0};
+            TreePose P;
+            slot_point(R, p, (double)t, xp, vp, &P, Tq);
             double fr[3];
             for (int a = 0; a < 3; ++a) fr[a] = xp[a] - floor(xp[a]);
             double sm[4] = {0, 0, 0, 0};
@@ -103,28 +220,62 @@ __global__ __launch_bounds__(ALM_BLOCK) void k_alm_points(Geo g, Physics ph, Rot
                 for (int q = 0; q < 4; ++q) sm[q] += w * s_corner[threadIdx.x * 8 + c][q];
             }
             const double rho = sm[0];
-            // e_theta = (0, -sin, cos); relative in-plane wind W = W_n e_x - W_t e_theta
-            const double ut = -sm[2] * st + sm[3] * ct;
-            const double wn = sm[1];
-            const double wt = -(ut - R.omega_rot * rr);
-            double a = atan2(wn, wt) * (180.0 / PI_D) - R.twist[k] - R.pitch_deg;
-            // |phi| <= 180 and |twist + pitch| < 180: one correction wraps to [-180, 180)
-            if (a >= 180.0) a -= 360.0;
-            else if (a < -180.0) a += 360.0;
-            const double CL = polar_lookup(a, R, R.cl), CD = polar_lookup(a, R, R.cd);
-            const double w2 = wn * wn + wt * wt, wm = sqrt(w2);
-            const double q = 0.5 * rho * w2 * R.chord[k] * R.dl[k];
-            double Fn = 0.0, Ft = 0.0;
-            if (wm > 0.0) {
-                Fn = q * (CL * wt + CD * wn) / wm;
-                Ft = q * (CL * wn - CD * wt) / wm;
+            double Fp[3] = {0.0, 0.0, 0.0};
+            if (!R.nodes) {
+                const int b = p / R.n_points, k = p % R.n_points;
+                const double th = R.azimuth0 + R.omega_rot * (double)t + 2.0 * PI_D * b / R.n_blades;
+                const double ct = cos(th), st = sin(th);
+                const double rr = R.r[k];
+                // e_theta = (0, -sin, cos); relative in-plane wind W = W_n e_x - W_t e_theta
+                const double ut = -sm[2] * st + sm[3] * ct;
+                const double wn = sm[1];
+                const double wt = -(ut - R.omega_rot * rr);
+                double Fn, Ft;
+                blade_element(R, rho, wn, wt, R.chord[k], R.dl[k], R.twist[k], R.pitch_deg, R.tip_loss, rr, Fn, Ft);
+                Fp[0] = Fn;
+                Fp[1] = -Ft * st;
+                Fp[2] = Ft * ct;
+                accT = Fn;
+                accQ = rr * Ft;
+            } else {
+                const TreePointDev &tp = R.tpts[p];
+                const NodeDev &N = R.nodes[tp.node];
+                const double W[3] = {sm[1] - vp[0], sm[2] - vp[1], sm[3] - vp[2]};
+                if (N.force == LBM_FORCE_BLADE) {
+                    double es[3], en[3], et[3];
+                    m3vec(P.T, N.dir, es);
+                    m3vec(P.T, N.normal, en);
+                    cross3(en, es, et);
+                    const double wn = dot3(W, en), wt = -dot3(W, et);
+                    double Fn, Ft;
+                    blade_element(R, rho, wn, wt, tp.chord, tp.measure, tp.twist, N.pitch_deg, N.tip_loss, tp.s, Fn,
+                                  Ft);
+                    for (int a = 0; a < 3; ++a) Fp[a] = Fn * en[a] + Ft * et[a];
+                } else if (N.force == LBM_FORCE_DRAG && N.kind == LBM_NODE_LINE) {
+                    // cross-flow drag of a cylinder: the part of W normal to the line
+                    double es[3], Wp[3];
+                    m3vec(P.T, N.dir, es);
+                    const double ws = dot3(W, es);
+                    for (int a = 0; a < 3; ++a) Wp[a] = W[a] - ws * es[a];
+                    const double c = 0.5 * rho * N.coef * tp.chord * tp.measure * sqrt(dot3(Wp, Wp));
+                    for (int a = 0; a < 3; ++a) Fp[a] = c * Wp[a];
+                } else if (N.force == LBM_FORCE_DRAG) {
+                    // disk: force along the normal (the node's x axis) on the normal wind
+                    const double n[3] = {P.T[0], P.T[3], P.T[6]};
+                    const double wn = dot3(W, n);
+                    const double c = 0.5 * rho * N.coef * tp.measure * fabs(wn) * wn;
+                    for (int a = 0; a < 3; ++a) Fp[a] = c * n[a];
+                }
+                double m[3];
+                cross3(Tq, Fp, m);
+                double *o = R.pt_force + (size_t)TREE_PT_OUT * p;
+                for (int a = 0; a < 3; ++a) {
+                    o[a] = xp[a];
+                    o[3 + a] = vp[a];
+                    o[6 + a] = Fp[a];
+                    o[9 + a] = m[a];
+                }
             }
-            if (R.tip_loss) {
-                const double Fl = tip_loss_factor(R.n_blades, R.radius, rr, atan2(wn, wt));
-                Fn *= Fl;
-                Ft *= Fl;
-            }
-            const double Fp[3] = {Fn, -Ft * st, Ft * ct};
             // Gaussian normalisation over the 13 nodes per axis (separable);
             // the Roma delta sums to one as it stands
             int c0[3];
@@ -142,16 +293,14 @@ __global__ __launch_bounds__(ALM_BLOCK) void k_alm_points(Geo g, Physics ph, Rot
                     S *= (double)sa;
                 }
             }
-            float *P = R.pts + (size_t)p * PT_STRIDE;
+            float *Pt = R.pts + (size_t)p * PT_STRIDE;
             for (int ax = 0; ax < 3; ++ax) {
-                P[ax] = (float)(xp[ax] - c0[ax]);  // offset from the nearest node
-                P[3 + ax] = (float)(-Fp[ax]);
-                P[6 + ax] = (float)c0[ax];
-                R.pt_force[3 * p + ax] = Fp[ax];
+                Pt[ax] = (float)(xp[ax] - c0[ax]);  // offset from the nearest node
+                Pt[3 + ax] = (float)(-Fp[ax]);
+                Pt[6 + ax] = (float)c0[ax];
+                if (!R.nodes) R.pt_force[3 * p + ax] = Fp[ax];
             }
-            P[9] = (float)(1.0 / S);
-            accT = Fn;
-            accQ = rr * Ft;
+            Pt[9] = (float)(1.0 / S);
         }
         s_red[threadIdx.x][0] = accT;
         s_red[threadIdx.x][1] = accQ;
@@ -174,7 +323,7 @@ __global__ __launch_bounds__(ALM_BLOCK) void k_alm_points(Geo g, Physics ph, Rot
 // Gather-form spreading over one rotor's box: F(X) = sum_p (-F_p) eta(X - x_p) / W_p
 __global__ __launch_bounds__(ALM_BLOCK) void k_alm_spread(const RotorDev *rots, int rid) {
     const RotorDev &R = rots[rid];
-    const int npts = R.n_blades * R.n_points;
+    const int npts = R.npts;
     __shared__ float sp[ALM_MAX_PTS * PT_STRIDE];
     for (int q = threadIdx.x; q < npts * PT_STRIDE; q += ALM_BLOCK) sp[q] = R.pts[q];
     __syncthreads();
@@ -209,7 +358,7 @@ static void alm_t(const Geo &g, const Physics &ph, const RotorDev *h_rots, Rotor
                   hipStream_t s) {
     int nb = 1;
     for (int r = 0; r < nrot; ++r) {
-        const int b = (h_rots[r].n_blades * h_rots[r].n_points + ALM_BATCH - 1) / ALM_BATCH;
+        const int b = (h_rots[r].npts + ALM_BATCH - 1) / ALM_BATCH;
         nb = b > nb ? b : nb;
     }
     k_alm_points<T, PAR><<<dim3(nb, nrot), ALM_BLOCK, 0, s>>>(g, ph, d_rots, t);

@@ -2,6 +2,7 @@
 // device bookkeeping and the per-step kernel sequence.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -23,6 +24,12 @@ struct RotorHost {
     double *d_r = nullptr, *d_chord = nullptr, *d_twist = nullptr, *d_dl = nullptr;
     float *d_cl = nullptr, *d_cd = nullptr, *d_pts = nullptr, *d_Fbox = nullptr;
     double *d_ptf = nullptr, *d_loads = nullptr;
+    size_t ptf_len = 0;                  // doubles in d_ptf
+    // turbine tree (Sec. 3.3): device nodes and points, node of each point
+    NodeDev *d_nodes = nullptr;
+    TreePointDev *d_tpts = nullptr;
+    int n_nodes = 0;
+    std::vector<int> pt_node;
 };
 
 size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -175,7 +182,8 @@ int refresh_rotor_table(lbm_ctx *c) {
 }
 
 void free_rotor(RotorHost &R) {
-    void *ptrs[] = {R.d_r, R.d_chord, R.d_twist, R.d_dl, R.d_cl, R.d_cd, R.d_pts, R.d_Fbox, R.d_ptf, R.d_loads};
+    void *ptrs[] = {R.d_r,   R.d_chord, R.d_twist, R.d_dl,    R.d_cl,   R.d_cd,
+                    R.d_pts, R.d_Fbox,  R.d_ptf,   R.d_loads, R.d_nodes, R.d_tpts};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     R = RotorHost{};
@@ -188,7 +196,7 @@ int zero_rotor_boxes(lbm_ctx *c) {
         const size_t nb = (size_t)R.dev.box.bnx * R.dev.box.bny * R.dev.box.bnz;
         HIPCHK(c, hipMemsetAsync(R.d_Fbox, 0, 3 * nb * sizeof(float), c->stream));
         HIPCHK(c, hipMemsetAsync(R.d_loads, 0, ALM_LOADS_LEN * sizeof(double), c->stream));
-        HIPCHK(c, hipMemsetAsync(R.d_ptf, 0, 3 * (size_t)R.npts * sizeof(double), c->stream));
+        HIPCHK(c, hipMemsetAsync(R.d_ptf, 0, R.ptf_len * sizeof(double), c->stream));
     }
     return LBM_OK;
 }
@@ -422,6 +430,7 @@ int lbm_set_rotor(lbm_ctx *c, int id, const lbm_rotor *r) {
     HIPCHK(c, hipMemset(R.d_Fbox, 0, (size_t)nb * 3 * sizeof(float)));
     HIPCHK(c, hipMemset(R.d_loads, 0, ALM_LOADS_LEN * sizeof(double)));
     HIPCHK(c, hipMemset(R.d_ptf, 0, (size_t)npts * 3 * sizeof(double)));
+    R.ptf_len = (size_t)npts * 3;
     RotorDev &D = R.dev;
     D = RotorDev{};
     for (int k = 0; k < 3; ++k) D.hub[k] = r->hub[k];
@@ -433,6 +442,7 @@ int lbm_set_rotor(lbm_ctx *c, int id, const lbm_rotor *r) {
     D.kernel = r->kernel;
     D.tip_loss = r->tip_loss;
     D.half = half;
+    D.npts = npts;
     D.n_blades = r->n_blades;
     D.n_points = np;
     D.n_polar = r->n_polar;
@@ -452,6 +462,349 @@ int lbm_set_rotor(lbm_ctx *c, int id, const lbm_rotor *r) {
     R.npts = npts;
     R.on = true;
     return refresh_rotor_table(c);
+}
+
+// ------------------------------------------------------------ turbine tree
+namespace {
+
+struct HostPose {
+    double T[9], o[3];
+};
+
+void h_m3mul(const double *A, const double *B, double *C) {
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) C[3 * i + j] = A[3 * i] * B[j] + A[3 * i + 1] * B[3 + j] + A[3 * i + 2] * B[6 + j];
+}
+void h_m3vec(const double *A, const double *x, double *y) {
+    for (int i = 0; i < 3; ++i) y[i] = A[3 * i] * x[0] + A[3 * i + 1] * x[1] + A[3 * i + 2] * x[2];
+}
+double h_norm(const double *a) { return std::sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]); }
+
+// Pose of every node in the reference configuration: each node's angle at
+// angle0 and no oscillation (the centre of every oscillation).
+void reference_poses(const lbm_turbine *tb, std::vector<HostPose> &P) {
+    P.resize(tb->n_nodes);
+    for (int k = 0; k < tb->n_nodes; ++k) {
+        const lbm_node &N = tb->nodes[k];
+        HostPose par{};
+        par.T[0] = par.T[4] = par.T[8] = 1.0;
+        if (N.parent >= 0) par = P[N.parent];
+        const double ex[3] = {1.0, 0.0, 0.0};
+        const bool turns = N.omega != 0.0 || N.amp != 0.0 || N.angle0 != 0.0;
+        const double *a = turns ? N.axis : ex, th = N.angle0, ct = std::cos(th), st = std::sin(th), k1 = 1.0 - ct;
+        const double R[9] = {ct + k1 * a[0] * a[0],        k1 * a[0] * a[1] - st * a[2], k1 * a[0] * a[2] + st * a[1],
+                             k1 * a[1] * a[0] + st * a[2], ct + k1 * a[1] * a[1],        k1 * a[1] * a[2] - st * a[0],
+                             k1 * a[2] * a[0] - st * a[1], k1 * a[2] * a[1] + st * a[0], ct + k1 * a[2] * a[2]};
+        double TpTr[9], Tpr[3];
+        h_m3mul(par.T, N.rot, TpTr);
+        h_m3mul(TpTr, R, P[k].T);
+        h_m3vec(par.T, N.pos, Tpr);
+        for (int c = 0; c < 3; ++c) P[k].o[c] = par.o[c] + Tpr[c];
+    }
+}
+
+// Interval [lo, hi] per axis that holds point q of node `node` at every time.
+// A constant-rate rotation (the lowest one on the point's chain) sweeps a
+// circle about its axis: exact bounding box of that circle, taken in the
+// reference configuration. Every other motion on the chain moves the point
+// by at most its angle excursion times the lever arm (2 lever arms for a full
+// turn) plus the oscillation amplitude of the origin; lever arms bound
+// |x - o_k| as |q| plus the lengths of the offsets below node k, which no
+// rotation changes.
+void point_reach(const lbm_turbine *tb, const std::vector<HostPose> &P, int node, const double q[3], double lo[3],
+                 double hi[3]) {
+    int chain[TREE_MAX_DEPTH], d = 0;
+    for (int k = node; k >= 0 && d < TREE_MAX_DEPTH; k = tb->nodes[k].parent) chain[d++] = k;
+    double xr[3], tq[3];
+    h_m3vec(P[node].T, q, tq);
+    for (int a = 0; a < 3; ++a) xr[a] = P[node].o[a] + tq[a];
+    int circ = -1;
+    for (int i = 0; i < d; ++i)
+        if (tb->nodes[chain[i]].omega != 0.0) {
+            circ = chain[i];
+            break;
+        }
+    double cen[3] = {xr[0], xr[1], xr[2]}, ext[3] = {0, 0, 0};
+    if (circ >= 0) {
+        const lbm_node &N = tb->nodes[circ];
+        HostPose par{};
+        par.T[0] = par.T[4] = par.T[8] = 1.0;
+        if (N.parent >= 0) par = P[N.parent];
+        double TpTr[9], ah[3];
+        h_m3mul(par.T, N.rot, TpTr);
+        h_m3vec(TpTr, N.axis, ah);
+        const double an = h_norm(ah);
+        for (int a = 0; a < 3; ++a) ah[a] /= an;
+        double rel[3];
+        for (int a = 0; a < 3; ++a) rel[a] = xr[a] - P[circ].o[a];
+        const double along = rel[0] * ah[0] + rel[1] * ah[1] + rel[2] * ah[2];
+        double rad[3];
+        for (int a = 0; a < 3; ++a) {
+            cen[a] = P[circ].o[a] + along * ah[a];
+            rad[a] = xr[a] - cen[a];
+        }
+        const double rho = h_norm(rad);
+        for (int a = 0; a < 3; ++a) ext[a] = rho * std::sqrt(std::fmax(0.0, 1.0 - ah[a] * ah[a]));
+    }
+    double dev = 0.0, lever = h_norm(q);
+    for (int i = 0; i < d; ++i) {
+        const lbm_node &N = tb->nodes[chain[i]];
+        if (chain[i] != circ) {
+            if (N.omega != 0.0) dev += 2.0 * lever;
+            else if (N.amp != 0.0) dev += std::fmin(std::fabs(N.amp), 2.0) * lever;
+        }
+        dev += h_norm(N.disp);
+        lever += h_norm(N.pos) + h_norm(N.disp);
+    }
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = cen[a] - ext[a] - dev;
+        hi[a] = cen[a] + ext[a] + dev;
+    }
+}
+
+bool unit(const double *a) { return std::fabs(h_norm(a) - 1.0) < 1e-9; }
+
+}  // namespace
+
+int lbm_set_turbine(lbm_ctx *c, int id, const lbm_turbine *tb) {
+    if (!c) return LBM_EINVAL;
+    if (id < 0 || id >= MAX_ROTORS || !tb || !tb->nodes) return fail(c, LBM_EINVAL, "bad turbine id or null turbine");
+    if (tb->n_nodes < 1 || tb->n_nodes > TREE_MAX_NODES)
+        return fail(c, LBM_EINVAL, "n_nodes must be in [1, %d]", TREE_MAX_NODES);
+    if (tb->kernel != LBM_KERNEL_GAUSS && tb->kernel != LBM_KERNEL_ROMA3)
+        return fail(c, LBM_EINVAL, "unknown spreading kernel %d", tb->kernel);
+    if (tb->kernel == LBM_KERNEL_GAUSS && !(tb->eps > 0.0)) return fail(c, LBM_EINVAL, "eps must be positive");
+    bool any_blade = false;
+    int npts = 0;
+    for (int k = 0; k < tb->n_nodes; ++k) {
+        const lbm_node &N = tb->nodes[k];
+        if (N.parent < -1 || N.parent >= k) return fail(c, LBM_EINVAL, "node %d: parent must precede it", k);
+        int depth = 1;
+        for (int q = N.parent; q >= 0; q = tb->nodes[q].parent) ++depth;
+        if (depth > TREE_MAX_DEPTH) return fail(c, LBM_EINVAL, "node %d: tree deeper than %d", k, TREE_MAX_DEPTH);
+        if (N.kind != LBM_NODE_FRAME && N.kind != LBM_NODE_LINE && N.kind != LBM_NODE_DISK)
+            return fail(c, LBM_EINVAL, "node %d: unknown kind %d", k, N.kind);
+        if (N.force != LBM_FORCE_NONE && N.force != LBM_FORCE_BLADE && N.force != LBM_FORCE_DRAG)
+            return fail(c, LBM_EINVAL, "node %d: unknown force model %d", k, N.force);
+        double RRt[9], Rt[9];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) Rt[3 * i + j] = N.rot[3 * j + i];
+        h_m3mul(N.rot, Rt, RRt);
+        for (int i = 0; i < 9; ++i)
+            if (std::fabs(RRt[i] - (i % 4 == 0 ? 1.0 : 0.0)) > 1e-9)
+                return fail(c, LBM_EINVAL, "node %d: rot is not orthonormal", k);
+        const double det = N.rot[0] * (N.rot[4] * N.rot[8] - N.rot[5] * N.rot[7]) -
+                           N.rot[1] * (N.rot[3] * N.rot[8] - N.rot[5] * N.rot[6]) +
+                           N.rot[2] * (N.rot[3] * N.rot[7] - N.rot[4] * N.rot[6]);
+        if (!(det > 0.0)) return fail(c, LBM_EINVAL, "node %d: rot must have determinant +1", k);
+        const bool turns = N.omega != 0.0 || N.amp != 0.0 || N.angle0 != 0.0;
+        if (turns && !unit(N.axis)) return fail(c, LBM_EINVAL, "node %d: axis must be a unit vector", k);
+        if (N.kind == LBM_NODE_FRAME) {
+            if (N.force != LBM_FORCE_NONE) return fail(c, LBM_EINVAL, "node %d: a frame carries no force model", k);
+            continue;
+        }
+        if (N.n_points < 1 || !N.s || !N.width) return fail(c, LBM_EINVAL, "node %d: needs n_points, s, width", k);
+        if (N.kind == LBM_NODE_DISK && N.n_azimuth < 1) return fail(c, LBM_EINVAL, "node %d: n_azimuth < 1", k);
+        if (N.kind == LBM_NODE_LINE && !unit(N.dir)) return fail(c, LBM_EINVAL, "node %d: dir must be a unit vector", k);
+        if (N.force == LBM_FORCE_BLADE) {
+            if (N.kind != LBM_NODE_LINE || !N.chord || !N.twist)
+                return fail(c, LBM_EINVAL, "node %d: blade elements need a line with chord and twist", k);
+            const double nd = N.normal[0] * N.dir[0] + N.normal[1] * N.dir[1] + N.normal[2] * N.dir[2];
+            if (!unit(N.normal) || std::fabs(nd) > 1e-9)
+                return fail(c, LBM_EINVAL, "node %d: normal must be a unit vector normal to dir", k);
+            if (N.tip_loss != 0 && N.tip_loss != 1) return fail(c, LBM_EINVAL, "node %d: tip_loss must be 0 or 1", k);
+            if (N.tip_loss && (tb->n_blades < 1 || !(tb->radius > 0.0)))
+                return fail(c, LBM_EINVAL, "node %d: tip loss needs n_blades and radius", k);
+            for (int m = 0; m < N.n_points; ++m)
+                if (!(std::fabs(N.twist[m] + N.pitch_deg) < 180.0))
+                    return fail(c, LBM_EINVAL, "node %d: |twist + pitch| must stay below 180 degrees", k);
+            any_blade = true;
+        }
+        if (N.force == LBM_FORCE_DRAG && N.kind == LBM_NODE_LINE && !N.chord)
+            return fail(c, LBM_EINVAL, "node %d: line drag needs the diameters (chord)", k);
+        const long np = N.kind == LBM_NODE_LINE ? (long)N.n_points : (long)N.n_points * N.n_azimuth;
+        if (npts + np > ALM_MAX_POINTS) return fail(c, LBM_EINVAL, "more than %d points", ALM_MAX_POINTS);
+        npts += (int)np;
+    }
+    if (npts < 1) return fail(c, LBM_EINVAL, "a turbine needs at least one point");
+    double a0 = 0.0, da = 1.0;
+    if (any_blade) {
+        if (tb->n_polar < 2 || !tb->alpha_deg || !tb->cl || !tb->cd) return fail(c, LBM_EINVAL, "missing polars");
+        a0 = tb->alpha_deg[0];
+        da = (tb->alpha_deg[tb->n_polar - 1] - a0) / (tb->n_polar - 1);
+        if (!(da > 0.0)) return fail(c, LBM_EINVAL, "polar angles must ascend");
+        for (int k = 0; k < tb->n_polar; ++k)
+            if (std::fabs(tb->alpha_deg[k] - (a0 + k * da)) > 1e-9 * (1.0 + std::fabs(a0)))
+                return fail(c, LBM_EINVAL, "polar angle grid must be uniform");
+    }
+    // points in node order (disks: rings before azimuth), element data
+    std::vector<TreePointDev> pts;
+    std::vector<int> pt_node;
+    for (int k = 0; k < tb->n_nodes; ++k) {
+        const lbm_node &N = tb->nodes[k];
+        if (N.kind == LBM_NODE_LINE) {
+            for (int m = 0; m < N.n_points; ++m) {
+                TreePointDev p{};
+                p.node = k;
+                for (int a = 0; a < 3; ++a) p.q[a] = N.s[m] * N.dir[a];
+                p.s = N.s[m];
+                p.measure = N.width[m];
+                p.chord = N.chord ? N.chord[m] : 0.0;
+                p.twist = N.twist ? N.twist[m] : 0.0;
+                pts.push_back(p);
+                pt_node.push_back(k);
+            }
+        } else if (N.kind == LBM_NODE_DISK) {
+            for (int j = 0; j < N.n_points; ++j)
+                for (int m = 0; m < N.n_azimuth; ++m) {
+                    const double phi = 2.0 * 3.14159265358979323846 * m / N.n_azimuth;
+                    TreePointDev p{};
+                    p.node = k;
+                    p.q[1] = N.s[j] * std::cos(phi);
+                    p.q[2] = N.s[j] * std::sin(phi);
+                    p.s = N.s[j];
+                    p.measure = 2.0 * 3.14159265358979323846 * N.s[j] * N.width[j] / N.n_azimuth;
+                    pts.push_back(p);
+                    pt_node.push_back(k);
+                }
+        }
+    }
+    // spreading box: the support of every point over all times
+    const int half = tb->kernel == LBM_KERNEL_ROMA3 ? 1 : SUPPORT;
+    std::vector<HostPose> ref;
+    reference_poses(tb, ref);
+    int b0[3] = {1 << 30, 1 << 30, 1 << 30}, b1[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
+    for (const TreePointDev &p : pts) {
+        double lo[3], hi[3];
+        point_reach(tb, ref, p.node, p.q, lo, hi);
+        for (int a = 0; a < 3; ++a) {
+            // nearest node of any position in [lo, hi], with room for rounding
+            b0[a] = std::min(b0[a], (int)std::floor(lo[a] + 0.5 - 1e-9) - half);
+            b1[a] = std::max(b1[a], (int)std::floor(hi[a] + 0.5 + 1e-9) + half);
+        }
+    }
+    const int dims[3] = {c->cfg.nx, c->cfg.ny, c->cfg.nz};
+    for (int a = 0; a < 3; ++a)
+        if (b0[a] < 0 || b1[a] >= dims[a])
+            return fail(c, LBM_EINVAL, "turbine spreading box [%d,%d]x[%d,%d]x[%d,%d] leaves the domain", b0[0], b1[0],
+                        b0[1], b1[1], b0[2], b1[2]);
+    std::vector<NodeDev> nodes(tb->n_nodes);
+    for (int k = 0; k < tb->n_nodes; ++k) {
+        const lbm_node &N = tb->nodes[k];
+        NodeDev &D = nodes[k];
+        D = NodeDev{};
+        D.parent = N.parent;
+        D.kind = N.kind;
+        D.force = N.force;
+        D.tip_loss = N.tip_loss;
+        // a node that never turns gets the rotation about +x by 0 (identity)
+        const bool turns = N.omega != 0.0 || N.amp != 0.0 || N.angle0 != 0.0;
+        for (int a = 0; a < 3; ++a) {
+            D.pos[a] = N.pos[a];
+            D.axis[a] = turns ? N.axis[a] : (a == 0 ? 1.0 : 0.0);
+            D.disp[a] = N.disp[a];
+            D.dir[a] = N.dir[a];
+            D.normal[a] = N.normal[a];
+        }
+        for (int a = 0; a < 9; ++a) D.rot[a] = N.rot[a];
+        D.omega = N.omega;
+        D.angle0 = N.angle0;
+        D.amp = N.amp;
+        D.freq = N.freq;
+        D.phase = N.phase;
+        D.coef = N.coef;
+        D.pitch_deg = N.pitch_deg;
+    }
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    RotorHost &R = c->rot[id];
+    free_rotor(R);
+    const int np_pol = any_blade ? tb->n_polar : 2;
+    const size_t nb = (size_t)(b1[0] - b0[0] + 1) * (b1[1] - b0[1] + 1) * (b1[2] - b0[2] + 1);
+    R.ptf_len = (size_t)npts * TREE_PT_OUT;
+    bool ok = hipMalloc((void **)&R.d_cl, np_pol * sizeof(float)) == hipSuccess &&
+              hipMalloc((void **)&R.d_cd, np_pol * sizeof(float)) == hipSuccess &&
+              hipMalloc((void **)&R.d_pts, (size_t)npts * PT_STRIDE * sizeof(float)) == hipSuccess &&
+              hipMalloc((void **)&R.d_ptf, R.ptf_len * sizeof(double)) == hipSuccess &&
+              hipMalloc((void **)&R.d_loads, ALM_LOADS_LEN * sizeof(double)) == hipSuccess &&
+              hipMalloc((void **)&R.d_Fbox, nb * 3 * sizeof(float)) == hipSuccess &&
+              hipMalloc((void **)&R.d_nodes, nodes.size() * sizeof(NodeDev)) == hipSuccess &&
+              hipMalloc((void **)&R.d_tpts, pts.size() * sizeof(TreePointDev)) == hipSuccess;
+    if (!ok) {
+        free_rotor(R);
+        return fail(c, LBM_ENOMEM, "turbine buffers");
+    }
+    std::vector<float> cl(np_pol, 0.0f), cd(np_pol, 0.0f);
+    if (any_blade)
+        for (int k = 0; k < np_pol; ++k) {
+            cl[k] = (float)tb->cl[k];
+            cd[k] = (float)tb->cd[k];
+        }
+    HIPCHK(c, hipMemcpy(R.d_cl, cl.data(), np_pol * sizeof(float), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(R.d_cd, cd.data(), np_pol * sizeof(float), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(R.d_nodes, nodes.data(), nodes.size() * sizeof(NodeDev), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(R.d_tpts, pts.data(), pts.size() * sizeof(TreePointDev), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemset(R.d_Fbox, 0, nb * 3 * sizeof(float)));
+    HIPCHK(c, hipMemset(R.d_loads, 0, ALM_LOADS_LEN * sizeof(double)));
+    HIPCHK(c, hipMemset(R.d_ptf, 0, R.ptf_len * sizeof(double)));
+    RotorDev &D = R.dev;
+    D = RotorDev{};
+    D.eps = tb->eps;
+    D.radius = tb->radius;
+    D.kernel = tb->kernel;
+    D.half = half;
+    D.npts = npts;
+    D.n_blades = tb->n_blades;
+    D.n_points = 1;
+    D.n_polar = np_pol;
+    D.alpha0 = a0;
+    D.dalpha = da;
+    D.cl = R.d_cl;
+    D.cd = R.d_cd;
+    D.nodes = R.d_nodes;
+    D.tpts = R.d_tpts;
+    D.pts = R.d_pts;
+    D.pt_force = R.d_ptf;
+    D.loads = R.d_loads;
+    D.box = ForceBox{b0[0], b0[1], b0[2], b1[0] - b0[0] + 1, b1[1] - b0[1] + 1, b1[2] - b0[2] + 1, R.d_Fbox};
+    D.Fbox = R.d_Fbox;
+    R.npts = npts;
+    R.n_nodes = tb->n_nodes;
+    R.pt_node = pt_node;
+    R.on = true;
+    return refresh_rotor_table(c);
+}
+
+int lbm_turbine_points(const lbm_ctx *c, int id, int *n_points_total) {
+    if (!c || id < 0 || id >= MAX_ROTORS || !n_points_total) return LBM_EINVAL;
+    const RotorHost &R = c->rot[id];
+    if (!R.on || !R.d_nodes) return LBM_EINVAL;
+    *n_points_total = R.npts;
+    return LBM_OK;
+}
+
+int lbm_turbine_loads(lbm_ctx *c, int id, double *node_loads, double *pts) {
+    int rc = ready(c);
+    if (rc) return rc;
+    if (id < 0 || id >= MAX_ROTORS || !node_loads) return fail(c, LBM_EINVAL, "bad turbine id or null output");
+    RotorHost &R = c->rot[id];
+    if (!R.on || !R.d_nodes) return fail(c, LBM_EINVAL, "slot %d holds no turbine tree", id);
+    std::vector<double> o(R.ptf_len);
+    HIPCHK(c, hipMemcpyAsync(o.data(), R.d_ptf, R.ptf_len * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    // per node, in point order: force, moment about the node origin, power
+    for (int k = 0; k < 7 * R.n_nodes; ++k) node_loads[k] = 0.0;
+    for (int p = 0; p < R.npts; ++p) {
+        const double *q = o.data() + (size_t)TREE_PT_OUT * p;
+        double *L = node_loads + 7 * R.pt_node[p];
+        for (int a = 0; a < 3; ++a) {
+            L[a] += q[6 + a];
+            L[3 + a] += q[9 + a];
+        }
+        L[6] += q[6] * q[3] + q[7] * q[4] + q[8] * q[5];
+        if (pts)
+            for (int a = 0; a < 9; ++a) pts[9 * (size_t)p + a] = q[a];
+    }
+    return LBM_OK;
 }
 
 // inlet planes of the current and the previous step
@@ -641,6 +994,7 @@ int lbm_rotor_loads(lbm_ctx *c, int id, double out[3], double *pt_force) {
     if (id < 0 || id >= MAX_ROTORS || !out) return fail(c, LBM_EINVAL, "bad rotor id or null output");
     RotorHost &R = c->rot[id];
     if (!R.on) return fail(c, LBM_EINVAL, "rotor %d not set", id);
+    if (R.d_nodes) return fail(c, LBM_EINVAL, "slot %d holds a turbine tree: use lbm_turbine_loads", id);
     // the step leaves FP64 partial thrust and torque per batch of 32 points;
     // they are added here in batch order (deterministic, no extra kernel on
     // the step's critical path)

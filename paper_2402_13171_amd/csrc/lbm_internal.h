@@ -60,7 +60,29 @@ struct Physics {
     const MlpDev *mlp;
 };
 
-// Per-rotor device description used by the actuator-line kernels.
+// Turbine topology tree (Sec. 3.3): one node as the point kernel reads it.
+constexpr int TREE_MAX_NODES = 32;
+constexpr int TREE_MAX_DEPTH = 16;
+struct NodeDev {
+    int parent, kind, force, tip_loss;
+    double pos[3], rot[9], axis[3];
+    double omega, angle0, amp, freq, phase;
+    double disp[3], dir[3], normal[3];
+    double coef, pitch_deg;
+};
+// One point of a turbine: its node, its offset q in the node frame and its
+// element data (line: length; disk: area).
+struct TreePointDev {
+    int node;
+    int pad_;
+    double q[3];
+    double s, measure, chord, twist;
+};
+constexpr int TREE_PT_OUT = 12;  // per point out: x[3], v[3], F[3], (x - o_node) x F [3]
+
+// Per-rotor device description used by the actuator-line kernels. A slot
+// holds either a rigid rotor about +x (closed-form kinematics) or a turbine
+// tree (nodes != nullptr).
 struct RotorDev {
     double hub[3];
     double omega_rot, azimuth0, pitch_deg, eps, radius;
@@ -68,12 +90,15 @@ struct RotorDev {
     int kernel;    // LBM_KERNEL_GAUSS / LBM_KERNEL_ROMA3
     int tip_loss;  // multiply blade-element forces by the Prandtl factor
     int half;      // spreading support: nodes nearest(x_p) +- half per axis
+    int npts;      // points of the slot (rotor: n_blades * n_points)
+    const NodeDev *nodes;       // turbine tree, or nullptr for a rotor
+    const TreePointDev *tpts;   // [npts] turbine points
     double alpha0, dalpha;
     const double *r, *chord, *twist, *dl;     // n_points
     const float *cl, *cd;                     // n_polar
     // outputs
     float *pts;        // per point: x[3], F[3] (force on blade), c0[3] (as float), inv W
-    double *pt_force;  // per point: F[3] in FP64
+    double *pt_force;  // per point: F[3] in FP64 (turbine: TREE_PT_OUT values)
     double *loads;     // T, Q, P, then per batch of 32 points: partial T, Q
     // spreading box
     ForceBox box;

@@ -28,7 +28,7 @@ EXPORTS = [
     "lbm_strerror", "lbm_last_error", "lbm_copy_probe", "lbm_pattern_probe",
     "lbm_mlp_create", "lbm_mlp_destroy", "lbm_mlp_set_params", "lbm_mlp_get_params",
     "lbm_mlp_forward", "lbm_mlp_loss_grad", "lbm_mlp_adam_step", "lbm_mlp_take_loss",
-    "lbm_mlp_last_error",
+    "lbm_mlp_last_error", "lbm_set_turbine", "lbm_turbine_loads", "lbm_turbine_points",
 ]
 
 
@@ -63,6 +63,28 @@ class Rotor(C.Structure):
 KERNELS = {"gauss": 0, "roma3": 1}
 
 
+class Node(C.Structure):
+    _fields_ = [("parent", C.c_int), ("kind", C.c_int), ("force", C.c_int),
+                ("n_points", C.c_int), ("n_azimuth", C.c_int), ("tip_loss", C.c_int),
+                ("pos", C.c_double * 3), ("rot", C.c_double * 9), ("axis", C.c_double * 3),
+                ("omega", C.c_double), ("angle0", C.c_double),
+                ("amp", C.c_double), ("freq", C.c_double), ("phase", C.c_double),
+                ("disp", C.c_double * 3), ("dir", C.c_double * 3), ("normal", C.c_double * 3),
+                ("coef", C.c_double), ("pitch_deg", C.c_double),
+                ("s", _D), ("width", _D), ("chord", _D), ("twist", _D)]
+
+
+class Turbine(C.Structure):
+    _fields_ = [("n_nodes", C.c_int), ("nodes", C.POINTER(Node)),
+                ("kernel", C.c_int), ("eps", C.c_double),
+                ("n_blades", C.c_int), ("radius", C.c_double),
+                ("n_polar", C.c_int), ("alpha_deg", _D), ("cl", _D), ("cd", _D)]
+
+
+NODE_KINDS = {"frame": 0, "line": 1, "disk": 2}
+FORCE_MODELS = {"none": 0, "blade": 1, "drag": 2}
+
+
 _lib = None
 
 
@@ -84,6 +106,9 @@ def lib():
         "lbm_init_tgv": [vp, C.c_double, C.c_double, C.c_double],
         "lbm_init_fields": [vp, _D, _D],
         "lbm_set_rotor": [vp, i, C.POINTER(Rotor)],
+        "lbm_set_turbine": [vp, i, C.POINTER(Turbine)],
+        "lbm_turbine_loads": [vp, i, _D, _D],
+        "lbm_turbine_points": [vp, i, C.POINTER(i)],
         "lbm_step": [vp, i],
         "lbm_set_inflow": [vp, _D, _D, i, C.c_double],
         "lbm_get_fields": [vp, _D, _D],
@@ -280,6 +305,61 @@ class Lbm:
         self._check(lib().lbm_sample_pops(self._ctx, cells.ctypes.data_as(C.POINTER(C.c_size_t)),
                                           cells.size, _p(f)))
         return f
+
+    def set_turbine(self, tid, turbine):
+        """turbine: dict of workloads.turbines (nodes with parent, kind,
+        force, pose, motion and per-point arrays; kernel, eps, polars)."""
+        nodes = turbine["nodes"]
+        arr = (Node * len(nodes))()
+        keep = [arr]
+        for k, nd in enumerate(nodes):
+            d = arr[k]
+            d.parent = nd.get("parent", -1)
+            d.kind = NODE_KINDS[nd.get("kind", "frame")]
+            d.force = FORCE_MODELS[nd.get("force", "none")]
+            d.n_azimuth = nd.get("n_azimuth", 0)
+            d.tip_loss = int(bool(nd.get("tip_loss", False)))
+            rot = np.asarray(nd.get("rot", np.eye(3)), dtype=np.float64).reshape(9)
+            for a in range(9):
+                d.rot[a] = rot[a]
+            for name in ("pos", "axis", "disp", "dir", "normal"):
+                vec = nd.get(name, (1.0, 0.0, 0.0) if name == "axis" else (0.0, 0.0, 0.0))
+                for a in range(3):
+                    getattr(d, name)[a] = vec[a]
+            for name in ("omega", "angle0", "amp", "freq", "phase", "coef", "pitch_deg"):
+                setattr(d, name, float(nd.get(name, 0.0)))
+            n = 0
+            for name in ("s", "width", "chord", "twist"):
+                if nd.get(name) is not None:
+                    a = _f64(nd[name])
+                    keep.append(a)
+                    setattr(d, name, _p(a))
+                    n = len(a)
+            d.n_points = n
+        t = Turbine()
+        t.n_nodes, t.nodes = len(nodes), arr
+        t.kernel = KERNELS[turbine.get("kernel", "gauss")]
+        t.eps = float(turbine.get("eps", 2.0))
+        t.n_blades = int(turbine.get("n_blades", 0))
+        t.radius = float(turbine.get("radius", 0.0))
+        pol = turbine.get("polar")
+        if pol is not None:
+            pa = {k: _f64(pol[k]) for k in ("alpha_deg", "cl", "cd")}
+            keep += list(pa.values())
+            t.n_polar = len(pa["alpha_deg"])
+            t.alpha_deg, t.cl, t.cd = _p(pa["alpha_deg"]), _p(pa["cl"]), _p(pa["cd"])
+        self._check(lib().lbm_set_turbine(self._ctx, tid, C.byref(t)))
+        npt = C.c_int()
+        self._check(lib().lbm_turbine_points(self._ctx, tid, C.byref(npt)))
+        self._npts[tid] = ("tree", len(nodes), npt.value)
+
+    def turbine_loads(self, tid):
+        """(node_loads[n_nodes][7]: force, moment about the node origin,
+        power; points[npts][9]: x, v, F) of the last step."""
+        _, nn, npts = self._npts[tid]
+        nl, pts = np.zeros((nn, 7)), np.zeros((npts, 9))
+        self._check(lib().lbm_turbine_loads(self._ctx, tid, _p(nl), _p(pts)))
+        return nl, pts
 
     def rotor_loads(self, rid, with_points=False):
         out = np.zeros(3)

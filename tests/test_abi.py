@@ -39,6 +39,10 @@ def test_struct_sizes_match_header_layout():
     # lbm_config: 3 ints, pad, 10 doubles, 2 ints, double, 3 ints, pad, 6 doubles, int, pad, pointer
     assert ctypes.sizeof(lbm.Config) == 3 * 4 + 4 + 10 * 8 + 2 * 4 + 8 + 3 * 4 + 4 + 6 * 8 + 4 + 4 + 8 + 8
     assert ctypes.sizeof(lbm.Rotor) == 6 * 8 + 5 * 8 + 2 * 4 + 4 * 8 + 8 + 3 * 8 + 2 * 4
+    # lbm_node: 6 ints, 31 doubles (pos, rot, axis, 5 motion values, disp, dir, normal, coef, pitch), 4 pointers
+    assert ctypes.sizeof(lbm.Node) == 6 * 4 + 31 * 8 + 4 * 8
+    # lbm_turbine: int + pad, pointer, int + pad, double, int + pad, double, int + pad, 3 pointers
+    assert ctypes.sizeof(lbm.Turbine) == 8 + 8 + 8 + 8 + 8 + 8 + 8 + 3 * 8
 
 
 def test_error_strings_without_gpu():
