@@ -113,12 +113,11 @@ __device__ void tree_pose(const NodeDev *nodes, int node, double t, TreePose &P)
 
 // Position (and, with v != nullptr, velocity and the node pose) of point p
 // of slot R at time t: a rotor's blade element or a turbine point.
-__device__ __forceinline__ void slot_point(const RotorDev &R, int p, double t, double xp[3], double *v,
-                                           TreePose *pose, double *Tq) {
+__device__ __forceinline__ void slot_point(const RotorDev &R, const TreePose *poses, int p, double t, double xp[3],
+                                           double *v, TreePose *pose, double *Tq) {
     if (R.nodes) {
         const TreePointDev &tp = R.tpts[p];
-        TreePose P;
-        tree_pose(R.nodes, tp.node, t, P);
+        const TreePose &P = poses[tp.node];
         double q[3] = {tp.q[0], tp.q[1], tp.q[2]}, tq[3];
         m3vec(P.T, q, tq);
         for (int a = 0; a < 3; ++a) xp[a] = P.o[a] + tq[a];
@@ -186,11 +185,16 @@ __global__ __launch_bounds__(ALM_BLOCK) void k_alm_points(Geo g, Physics ph, Rot
     if (base >= npts) return;  // uniform across the workgroup
     __shared__ double s_corner[ALM_BLOCK][4];  // rho, u of one corner cell per work item
     __shared__ double s_red[ALM_BATCH][2];
+    __shared__ TreePose s_pose[TREE_MAX_NODES];  // turbine: every node's pose at this step
+    if (R.nodes) {
+        if (threadIdx.x < R.n_nodes) tree_pose(R.nodes, threadIdx.x, (double)t, s_pose[threadIdx.x]);
+        __syncthreads();
+    }
     {
         const int p = base + threadIdx.x / 8, corner = threadIdx.x % 8;
         if (p < npts) {
             double xp[3];
-            slot_point(R, p, (double)t, xp, nullptr, nullptr, nullptr);
+            slot_point(R, s_pose, p, (double)t, xp, nullptr, nullptr, nullptr);
             const int dx = corner & 1, dy = (corner >> 1) & 1, dz = corner >> 2;
             const int cx = wrap_any((int)floor(xp[0]) + dx, g.nx);
             const int cy = wrap_any((int)floor(xp[1]) + dy, g.ny);
@@ -210,7 +214,7 @@ __global__ __launch_bounds__(ALM_BLOCK) void k_alm_points(Geo g, Physics ph, Rot
         if (p < npts) {
             double xp[3], vp[3] = {0, 0, 0}, Tq[3] = {0, 0, 0};
             TreePose P;
-            slot_point(R, p, (double)t, xp, vp, &P, Tq);
+            slot_point(R, s_pose, p, (double)t, xp, vp, &P, Tq);
             double fr[3];
             for (int a = 0; a < 3; ++a) fr[a] = xp[a] - floor(xp[a]);
             double sm[4] = {0, 0, 0, 0};
@@ -320,25 +324,60 @@ __global__ __launch_bounds__(ALM_BLOCK) void k_alm_points(Geo g, Physics ph, Rot
     }
 }
 
-// Gather-form spreading over one rotor's box: F(X) = sum_p (-F_p) eta(X - x_p) / W_p
-__global__ __launch_bounds__(ALM_BLOCK) void k_alm_spread(const RotorDev *rots, int rid) {
+// Gather-form spreading over one slot's box: F(X) = sum_p (-F_p) eta(X - x_p) / W_p.
+// One workgroup per tile of SP_TX x SP_TY x SP_TZ box cells. The workgroup
+// first keeps, in point order, the points whose support reaches the tile
+// (a ballot compaction per wave, then the waves' counts in order), stages
+// them in LDS, and each cell then sums over those points only: the same
+// terms in the same order as a sum over every point that skips the ones out
+// of reach, so the result does not depend on the tiling.
+constexpr int SP_TX = 16, SP_TY = 4, SP_TZ = 4;
+static_assert(SP_TX * SP_TY * SP_TZ == ALM_BLOCK, "one cell per thread");
+
+__global__ __launch_bounds__(ALM_BLOCK) void k_alm_spread(const RotorDev *rots, int rid, int tiles_x, int tiles_y) {
     const RotorDev &R = rots[rid];
     const int npts = R.npts;
-    __shared__ float sp[ALM_MAX_PTS * PT_STRIDE];
-    for (int q = threadIdx.x; q < npts * PT_STRIDE; q += ALM_BLOCK) sp[q] = R.pts[q];
-    __syncthreads();
     const ForceBox &B = R.box;
-    const size_t nb = (size_t)B.bnx * B.bny * B.bnz;
-    const size_t c = blockIdx.x * (size_t)ALM_BLOCK + threadIdx.x;
-    if (c >= nb) return;
-    const int lx = (int)(c % B.bnx), ly = (int)((c / B.bnx) % B.bny), lz = (int)(c / ((size_t)B.bnx * B.bny));
-    const int X = B.x0 + lx, Y = B.y0 + ly, Z = B.z0 + lz;
-    const float ie2 = R.kernel == LBM_KERNEL_GAUSS ? (float)(1.0 / (R.eps * R.eps)) : 0.0f;
     const int half = R.half;
+    __shared__ float sp[ALM_MAX_PTS * PT_STRIDE];
+    __shared__ int s_idx[ALM_MAX_PTS];
+    __shared__ int s_wave[ALM_BLOCK / 64];
+    const int tx = blockIdx.x % tiles_x, ty = (blockIdx.x / tiles_x) % tiles_y, tz = blockIdx.x / (tiles_x * tiles_y);
+    // tile extent in lattice coordinates (clipped to the box)
+    const int X0 = B.x0 + tx * SP_TX, Y0 = B.y0 + ty * SP_TY, Z0 = B.z0 + tz * SP_TZ;
+    const int X1 = min(X0 + SP_TX, B.x0 + B.bnx) - 1, Y1 = min(Y0 + SP_TY, B.y0 + B.bny) - 1,
+              Z1 = min(Z0 + SP_TZ, B.z0 + B.bnz) - 1;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int count = 0;  // uniform across the workgroup
+    for (int k0 = 0; k0 < npts; k0 += ALM_BLOCK) {
+        const int p = k0 + threadIdx.x;
+        bool reach = false;
+        if (p < npts) {
+            const float *P = R.pts + (size_t)p * PT_STRIDE;
+            const int cx = (int)P[6], cy = (int)P[7], cz = (int)P[8];
+            reach = cx - half <= X1 && cx + half >= X0 && cy - half <= Y1 && cy + half >= Y0 && cz - half <= Z1 &&
+                    cz + half >= Z0;
+        }
+        const unsigned long long bal = __ballot(reach);
+        if (lane == 0) s_wave[wave] = __popcll(bal);
+        __syncthreads();
+        int off = count;
+        for (int w = 0; w < wave; ++w) off += s_wave[w];
+        if (reach) s_idx[off + __popcll(bal & ((1ull << lane) - 1ull))] = p;
+        for (int w = 0; w < ALM_BLOCK / 64; ++w) count += s_wave[w];
+        __syncthreads();
+    }
+    for (int q = threadIdx.x; q < count * PT_STRIDE; q += ALM_BLOCK)
+        sp[q] = R.pts[(size_t)s_idx[q / PT_STRIDE] * PT_STRIDE + q % PT_STRIDE];
+    __syncthreads();
+    const int X = X0 + (int)(threadIdx.x % SP_TX), Y = Y0 + (int)((threadIdx.x / SP_TX) % SP_TY),
+              Z = Z0 + (int)(threadIdx.x / (SP_TX * SP_TY));
+    if (X > X1 || Y > Y1 || Z > Z1) return;
+    const float ie2 = R.kernel == LBM_KERNEL_GAUSS ? (float)(1.0 / (R.eps * R.eps)) : 0.0f;
     const bool roma = R.kernel == LBM_KERNEL_ROMA3;  // uniform over the grid
     float Fx = 0.f, Fy = 0.f, Fz = 0.f;
-    for (int p = 0; p < npts; ++p) {
-        const float *P = sp + p * PT_STRIDE;
+    for (int k = 0; k < count; ++k) {
+        const float *P = sp + k * PT_STRIDE;
         const int dx = X - (int)P[6], dy = Y - (int)P[7], dz = Z - (int)P[8];
         if (abs(dx) > half || abs(dy) > half || abs(dz) > half) continue;
         const float ex = (float)dx - P[0], ey = (float)dy - P[1], ez = (float)dz - P[2];
@@ -348,6 +387,8 @@ __global__ __launch_bounds__(ALM_BLOCK) void k_alm_spread(const RotorDev *rots, 
         Fy = fmaf(w, P[4], Fy);
         Fz = fmaf(w, P[5], Fz);
     }
+    const size_t nb = (size_t)B.bnx * B.bny * B.bnz;
+    const size_t c = (size_t)(X - B.x0) + (size_t)B.bnx * ((size_t)(Y - B.y0) + (size_t)B.bny * (size_t)(Z - B.z0));
     R.Fbox[c] = Fx;
     R.Fbox[nb + c] = Fy;
     R.Fbox[2 * nb + c] = Fz;
@@ -363,8 +404,9 @@ static void alm_t(const Geo &g, const Physics &ph, const RotorDev *h_rots, Rotor
     }
     k_alm_points<T, PAR><<<dim3(nb, nrot), ALM_BLOCK, 0, s>>>(g, ph, d_rots, t);
     for (int r = 0; r < nrot; ++r) {
-        const size_t nb = (size_t)h_rots[r].box.bnx * h_rots[r].box.bny * h_rots[r].box.bnz;
-        k_alm_spread<<<(unsigned)((nb + ALM_BLOCK - 1) / ALM_BLOCK), ALM_BLOCK, 0, s>>>(d_rots, r);
+        const ForceBox &B = h_rots[r].box;
+        const int tx = (B.bnx + SP_TX - 1) / SP_TX, ty = (B.bny + SP_TY - 1) / SP_TY, tz = (B.bnz + SP_TZ - 1) / SP_TZ;
+        k_alm_spread<<<(unsigned)(tx * ty * tz), ALM_BLOCK, 0, s>>>(d_rots, r, tx, ty);
     }
 }
 

@@ -761,6 +761,7 @@ int lbm_set_turbine(lbm_ctx *c, int id, const lbm_turbine *tb) {
     D.cl = R.d_cl;
     D.cd = R.d_cd;
     D.nodes = R.d_nodes;
+    D.n_nodes = tb->n_nodes;
     D.tpts = R.d_tpts;
     D.pts = R.d_pts;
     D.pt_force = R.d_ptf;

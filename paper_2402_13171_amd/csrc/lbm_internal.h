@@ -91,6 +91,7 @@ struct RotorDev {
     int tip_loss;  // multiply blade-element forces by the Prandtl factor
     int half;      // spreading support: nodes nearest(x_p) +- half per axis
     int npts;      // points of the slot (rotor: n_blades * n_points)
+    int n_nodes;   // turbine tree nodes (0 for a rotor)
     const NodeDev *nodes;       // turbine tree, or nullptr for a rotor
     const TreePointDev *tpts;   // [npts] turbine points
     double alpha0, dalpha;

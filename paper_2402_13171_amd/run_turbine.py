@@ -12,6 +12,12 @@ without it (the paper's way of isolating the turbine overhead, Sec. 4.3,
 Table 1), the thrust/torque/power time series, and the final normal and
 tangential force per blade point.
 
+tree: the single-turbine box with a turbine given as a component tree
+(Sec. 3.3): --config hawt (tower, nacelle face and rotor), floating (the same
+on a pitching and surging platform), vawt (vertical-axis rotor, D = 32, with
+its shaft) or disk (actuator disk, D = 32, C_T' = 4/3). Reports MLUPS with
+and without it and per-component loads over the last rotor revolution.
+
 row: 1024 x 256 x 256, FP16 storage, learned closure, three rotors of
 diameter 48 spaced 5 D apart, ground wall (bounce-back) and free-slip top,
 sheared inflow u = 0.05 ((z + 1/2)/128)^0.14 plus a convected frozen
@@ -95,6 +101,65 @@ def single(args, log):
     return out
 
 
+def tree(args, log):
+    from workloads import turbines as TB
+    nx, ny, nz = 256, 128, 128
+    hub = (64.0, 63.5, 63.5)
+    rot = dict(workloads.single_turbine_rotor(), kernel=args.kernel, tip_loss=args.tip_loss)
+    if args.config == "hawt":
+        tb = TB.hawt(rot, base_z=8.0, overhang=3.0)
+        names = ["platform", "tower", "nacelle", "nacelle face", "hub", "blade 0", "blade 1", "blade 2"]
+    elif args.config == "floating":
+        tb = TB.hawt(rot, base_z=8.0, overhang=3.0, pitch_amp=0.05, surge_amp=1.0,
+                     wave_freq=2.0 * np.pi / 400.0)
+        names = ["platform", "tower", "nacelle", "nacelle face", "hub", "blade 0", "blade 1", "blade 2"]
+    elif args.config == "vawt":
+        tb = TB.vawt(hub, radius=16.0, height=32.0, n_points=32, tsr=3.0, chord=2.0, kernel=args.kernel)
+        names = ["rotor", "blade 0", "blade 1", "blade 2", "shaft"]
+    else:
+        tb = TB.actuator_disk(hub, radius=16.0, n_rings=8, n_azimuth=16, kernel=args.kernel)
+        names = ["disk"]
+    npts = sum(len(n["s"]) * n.get("n_azimuth", 1) if n["kind"] == "disk" else len(n.get("s", []))
+               for n in tb["nodes"] if n["kind"] != "frame")
+    u0 = np.zeros((3, nz, ny, nx))
+    u0[0] = 0.05
+    out = {"workload": f"turbine tree '{args.config}' in the single-turbine box 256x128x128 FP32, inflow 0.05, "
+                       f"{npts} points, {args.kernel} spreading", "config": args.config, "points": npts}
+    sim = Lbm(nx, ny, nz, omega=args.omega, bc_x="inout", u_in=(0.05, 0, 0))
+    sim.init_fields(np.ones((nz, ny, nx)), u0)
+    sim.step(10)
+    ms0 = timed_steps(sim, 200)
+    sim.close()
+    sim = Lbm(nx, ny, nz, omega=args.omega, bc_x="inout", u_in=(0.05, 0, 0))
+    sim.init_fields(np.ones((nz, ny, nx)), u0)
+    sim.set_turbine(0, tb)
+    t0 = time.time()
+    chunk, ms_t, series = 10, [], []
+    while sim.time < args.steps:
+        ms_t.append(timed_steps(sim, chunk))
+        nl, _ = sim.turbine_loads(0)
+        series.append([sim.time] + nl.reshape(-1).tolist())
+        if sim.time % 500 == 0:
+            log(f"tree {args.config}: step {sim.time}, total force x {nl[:, 0].sum():.4e}, power {nl[:, 6].sum():.4e}")
+    n = nx * ny * nz
+    s = np.array(series)
+    per_rev = int(round(2 * np.pi / rot["omega_rot"])) if args.config != "vawt" else \
+        int(round(2 * np.pi / tb["nodes"][0]["omega"]))
+    last = s[s[:, 0] > s[-1, 0] - per_rev][:, 1:].reshape(-1, len(tb["nodes"]), 7).mean(0)
+    out.update({
+        "steps": sim.time, "mlups_without_turbine": n / (ms0 * 1e-3) / 1e6,
+        "mlups_with_turbine": n / (np.median(ms_t) * 1e-3) / 1e6,
+        "turbine_overhead_pct": 100.0 * (np.median(ms_t) - ms0) / ms0,
+        "mean_last_revolution_per_node": {names[k]: {"force": last[k, 0:3].tolist(), "moment": last[k, 3:6].tolist(),
+                                                     "power": float(last[k, 6])}
+                                          for k in range(len(tb["nodes"]))},
+        "total_force_x": float(last[:, 0].sum()), "total_power": float(last[:, 6].sum()),
+        "wall_s": time.time() - t0,
+    })
+    sim.close()
+    return out
+
+
 def row(args, log):
     nx, ny, nz = 1024, 256, 256
     rots = workloads.turbine_row_rotors()
@@ -137,7 +202,9 @@ def row(args, log):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("case", choices=["single", "row"])
+    ap.add_argument("case", choices=["single", "row", "tree"])
+    ap.add_argument("--config", choices=["hawt", "floating", "vawt", "disk"], default="hawt",
+                    help="turbine tree (tree case)")
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--omega", type=float, default=1.9)
     ap.add_argument("--weights", default=None)
@@ -150,8 +217,10 @@ def main(argv=None):
         a.steps = 2000 if a.case == "single" else 5000
     t_start = time.time()
     log = lambda *m: print(f"[{time.time() - t_start:7.1f}s]", *m, flush=True)
-    res = single(a, log) if a.case == "single" else row(a, log)
-    out = a.out or (f"results/single_turbine_{a.kernel}{'_tiploss' if a.tip_loss else ''}.json" if a.case == 'single' else "results/turbine_row.json")
+    res = {"single": single, "row": row, "tree": tree}[a.case](a, log)
+    default = {"single": f"results/single_turbine_{a.kernel}{'_tiploss' if a.tip_loss else ''}.json",
+               "row": "results/turbine_row.json", "tree": f"results/tree_{a.config}.json"}
+    out = a.out or default[a.case]
     os.makedirs(os.path.dirname(out) or ".", exist_ok=True)
     with open(out, "w") as fh:
         json.dump(res, fh)
