@@ -33,12 +33,20 @@ def _rotor(hub, R=8.0, omega_rot=0.02, n_points=8, **kw):
     return rot
 
 
-def run_tree(shape, turbine, steps, storage="f32", omega=1.8):
+def run_tree(shape, turbine, steps, storage="f32", omega=1.8, open_domain=False):
     from paper_2402_13171_amd.lbm import Lbm
     nx, ny, nz = shape
-    print(f"turbine case {shape} {storage} nodes={len(turbine['nodes'])}", flush=True)
-    sim = Lbm(nx, ny, nz, omega=omega, storage=storage)
-    ref = oracle.Grid(nx, ny, nz, omega=omega)
+    print(f"turbine case {shape} {storage} nodes={len(turbine['nodes'])} open={open_domain}", flush=True)
+    if open_domain:
+        # inflow / zero-gradient outflow in x, ground wall (bounce-back) and
+        # free-slip top in z
+        sim = Lbm(nx, ny, nz, omega=omega, storage=storage, bc_x="inout", bc_z=("noslip", "freeslip"),
+                  u_in=(0.05, 0.0, 0.0))
+        ref = oracle.Grid(nx, ny, nz, omega=omega, bc_x=oracle.INOUT, bc_zlo=oracle.NOSLIP,
+                          bc_zhi=oracle.FREESLIP, u_in=(0.05, 0.0, 0.0))
+    else:
+        sim = Lbm(nx, ny, nz, omega=omega, storage=storage)
+        ref = oracle.Grid(nx, ny, nz, omega=omega)
     rho, u = _uniform(shape)
     sim.init_fields(rho, u)
     ref.init_fields(rho, u)
@@ -123,6 +131,20 @@ def test_hawt_with_tower_and_nacelle(kernel):
     nl, pts = hist[-1][1]
     assert nl[1, 0] > 0 and nl[3, 0] > 0  # tower and nacelle drag downstream
     print(f"HAWT + tower + nacelle ({kernel}): worst force error {w:.2e}, field {e:.2e}")
+
+
+@pytest.mark.parametrize("kernel,base_z", [("gauss", 7.0), ("roma3", 1.5)])
+def test_hawt_on_the_ground_in_an_open_domain(kernel, base_z):
+    """Tower standing on the bounce-back ground of an inflow/outflow domain
+    with a free-slip top (the Roma delta lets the tower reach one cell above
+    the wall)."""
+    _need_gpu()
+    rot = _rotor((16.0, 23.5, 30.0))
+    tr = TB.hawt(rot, base_z=base_z, overhang=3.0, tower_spacing=3.0, kernel=kernel)
+    sim, ref, hist = run_tree((48, 48, 48), tr, 9, open_domain=True)
+    w = check_tree(hist, 2e-5)
+    e = check_fields(sim, ref, 1e-5)
+    print(f"HAWT on the ground, open domain ({kernel}): worst force error {w:.2e}, field {e:.2e}")
 
 
 def test_vawt():
