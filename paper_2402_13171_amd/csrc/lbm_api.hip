@@ -168,16 +168,20 @@ int ready(lbm_ctx *c) {
 
 int refresh_rotor_table(lbm_ctx *c) {
     c->h_rots.clear();
+    std::vector<RotorDev> rots;
     for (int r = 0; r < MAX_ROTORS; ++r)
-        if (c->rot[r].on) c->h_rots.push_back(c->rot[r].dev);
-    if (c->h_rots.empty()) return LBM_OK;
+        if (c->rot[r].on) rots.push_back(c->rot[r].dev);
+    if (rots.empty()) return LBM_OK;
     if (!c->d_rots) {
         if (hipMalloc((void **)&c->d_rots, sizeof(RotorDev) * MAX_ROTORS) != hipSuccess)
             return fail(c, LBM_ENOMEM, "rotor table");
     }
-    HIPCHK(c, hipMemcpyAsync(c->d_rots, c->h_rots.data(), sizeof(RotorDev) * c->h_rots.size(),
-                             hipMemcpyHostToDevice, c->stream));
+    // the host list (which drives the launches) only names slots whose
+    // device table entry was written
+    HIPCHK(c, hipMemcpyAsync(c->d_rots, rots.data(), sizeof(RotorDev) * rots.size(), hipMemcpyHostToDevice,
+                             c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->h_rots = rots;
     return LBM_OK;
 }
 
@@ -401,66 +405,76 @@ int lbm_set_rotor(lbm_ctx *c, int id, const lbm_rotor *r) {
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     RotorHost &R = c->rot[id];
     free_rotor(R);
-    const int np = r->n_points, npts = r->n_blades * np, nb = (bx1 - bx0 + 1) * (by1 - by0 + 1) * (bz1 - bz0 + 1);
-    bool ok = hipMalloc((void **)&R.d_r, np * sizeof(double)) == hipSuccess &&
-              hipMalloc((void **)&R.d_chord, np * sizeof(double)) == hipSuccess &&
-              hipMalloc((void **)&R.d_twist, np * sizeof(double)) == hipSuccess &&
-              hipMalloc((void **)&R.d_dl, np * sizeof(double)) == hipSuccess &&
-              hipMalloc((void **)&R.d_cl, r->n_polar * sizeof(float)) == hipSuccess &&
-              hipMalloc((void **)&R.d_cd, r->n_polar * sizeof(float)) == hipSuccess &&
-              hipMalloc((void **)&R.d_pts, (size_t)npts * PT_STRIDE * sizeof(float)) == hipSuccess &&
-              hipMalloc((void **)&R.d_ptf, (size_t)npts * 3 * sizeof(double)) == hipSuccess &&
-              hipMalloc((void **)&R.d_loads, ALM_LOADS_LEN * sizeof(double)) == hipSuccess &&
-              hipMalloc((void **)&R.d_Fbox, (size_t)nb * 3 * sizeof(float)) == hipSuccess;
-    if (!ok) {
+    // on any failure below the slot ends up empty, and the rotor table
+    // must stop naming the freed buffers
+    const int rc = [&]() -> int {
+        const int np = r->n_points, npts = r->n_blades * np, nb = (bx1 - bx0 + 1) * (by1 - by0 + 1) * (bz1 - bz0 + 1);
+        bool ok = hipMalloc((void **)&R.d_r, np * sizeof(double)) == hipSuccess &&
+                  hipMalloc((void **)&R.d_chord, np * sizeof(double)) == hipSuccess &&
+                  hipMalloc((void **)&R.d_twist, np * sizeof(double)) == hipSuccess &&
+                  hipMalloc((void **)&R.d_dl, np * sizeof(double)) == hipSuccess &&
+                  hipMalloc((void **)&R.d_cl, r->n_polar * sizeof(float)) == hipSuccess &&
+                  hipMalloc((void **)&R.d_cd, r->n_polar * sizeof(float)) == hipSuccess &&
+                  hipMalloc((void **)&R.d_pts, (size_t)npts * PT_STRIDE * sizeof(float)) == hipSuccess &&
+                  hipMalloc((void **)&R.d_ptf, (size_t)npts * 3 * sizeof(double)) == hipSuccess &&
+                  hipMalloc((void **)&R.d_loads, ALM_LOADS_LEN * sizeof(double)) == hipSuccess &&
+                  hipMalloc((void **)&R.d_Fbox, (size_t)nb * 3 * sizeof(float)) == hipSuccess;
+        if (!ok) {
+            free_rotor(R);
+            return fail(c, LBM_ENOMEM, "rotor buffers");
+        }
+        std::vector<float> cl(r->n_polar), cd(r->n_polar);
+        for (int k = 0; k < r->n_polar; ++k) {
+            cl[k] = (float)r->cl[k];
+            cd[k] = (float)r->cd[k];
+        }
+        HIPCHK(c, hipMemcpy(R.d_r, r->r, np * sizeof(double), hipMemcpyHostToDevice));
+        HIPCHK(c, hipMemcpy(R.d_chord, r->chord, np * sizeof(double), hipMemcpyHostToDevice));
+        HIPCHK(c, hipMemcpy(R.d_twist, r->twist_deg, np * sizeof(double), hipMemcpyHostToDevice));
+        HIPCHK(c, hipMemcpy(R.d_dl, r->dl, np * sizeof(double), hipMemcpyHostToDevice));
+        HIPCHK(c, hipMemcpy(R.d_cl, cl.data(), r->n_polar * sizeof(float), hipMemcpyHostToDevice));
+        HIPCHK(c, hipMemcpy(R.d_cd, cd.data(), r->n_polar * sizeof(float), hipMemcpyHostToDevice));
+        HIPCHK(c, hipMemset(R.d_Fbox, 0, (size_t)nb * 3 * sizeof(float)));
+        HIPCHK(c, hipMemset(R.d_loads, 0, ALM_LOADS_LEN * sizeof(double)));
+        HIPCHK(c, hipMemset(R.d_ptf, 0, (size_t)npts * 3 * sizeof(double)));
+        R.ptf_len = (size_t)npts * 3;
+        RotorDev &D = R.dev;
+        D = RotorDev{};
+        for (int k = 0; k < 3; ++k) D.hub[k] = r->hub[k];
+        D.omega_rot = r->omega_rot;
+        D.azimuth0 = r->azimuth0;
+        D.pitch_deg = r->pitch_deg;
+        D.eps = r->eps;
+        D.radius = r->radius;
+        D.kernel = r->kernel;
+        D.tip_loss = r->tip_loss;
+        D.half = half;
+        D.npts = npts;
+        D.n_blades = r->n_blades;
+        D.n_points = np;
+        D.n_polar = r->n_polar;
+        D.alpha0 = a0;
+        D.dalpha = da;
+        D.r = R.d_r;
+        D.chord = R.d_chord;
+        D.twist = R.d_twist;
+        D.dl = R.d_dl;
+        D.cl = R.d_cl;
+        D.cd = R.d_cd;
+        D.pts = R.d_pts;
+        D.pt_force = R.d_ptf;
+        D.loads = R.d_loads;
+        D.box = ForceBox{bx0, by0, bz0, bx1 - bx0 + 1, by1 - by0 + 1, bz1 - bz0 + 1, R.d_Fbox};
+        D.Fbox = R.d_Fbox;
+        R.npts = npts;
+        R.on = true;
+        return LBM_OK;
+    }();
+    if (rc != LBM_OK) {
         free_rotor(R);
-        return fail(c, LBM_ENOMEM, "rotor buffers");
+        (void)refresh_rotor_table(c);
+        return rc;
     }
-    std::vector<float> cl(r->n_polar), cd(r->n_polar);
-    for (int k = 0; k < r->n_polar; ++k) {
-        cl[k] = (float)r->cl[k];
-        cd[k] = (float)r->cd[k];
-    }
-    HIPCHK(c, hipMemcpy(R.d_r, r->r, np * sizeof(double), hipMemcpyHostToDevice));
-    HIPCHK(c, hipMemcpy(R.d_chord, r->chord, np * sizeof(double), hipMemcpyHostToDevice));
-    HIPCHK(c, hipMemcpy(R.d_twist, r->twist_deg, np * sizeof(double), hipMemcpyHostToDevice));
-    HIPCHK(c, hipMemcpy(R.d_dl, r->dl, np * sizeof(double), hipMemcpyHostToDevice));
-    HIPCHK(c, hipMemcpy(R.d_cl, cl.data(), r->n_polar * sizeof(float), hipMemcpyHostToDevice));
-    HIPCHK(c, hipMemcpy(R.d_cd, cd.data(), r->n_polar * sizeof(float), hipMemcpyHostToDevice));
-    HIPCHK(c, hipMemset(R.d_Fbox, 0, (size_t)nb * 3 * sizeof(float)));
-    HIPCHK(c, hipMemset(R.d_loads, 0, ALM_LOADS_LEN * sizeof(double)));
-    HIPCHK(c, hipMemset(R.d_ptf, 0, (size_t)npts * 3 * sizeof(double)));
-    R.ptf_len = (size_t)npts * 3;
-    RotorDev &D = R.dev;
-    D = RotorDev{};
-    for (int k = 0; k < 3; ++k) D.hub[k] = r->hub[k];
-    D.omega_rot = r->omega_rot;
-    D.azimuth0 = r->azimuth0;
-    D.pitch_deg = r->pitch_deg;
-    D.eps = r->eps;
-    D.radius = r->radius;
-    D.kernel = r->kernel;
-    D.tip_loss = r->tip_loss;
-    D.half = half;
-    D.npts = npts;
-    D.n_blades = r->n_blades;
-    D.n_points = np;
-    D.n_polar = r->n_polar;
-    D.alpha0 = a0;
-    D.dalpha = da;
-    D.r = R.d_r;
-    D.chord = R.d_chord;
-    D.twist = R.d_twist;
-    D.dl = R.d_dl;
-    D.cl = R.d_cl;
-    D.cd = R.d_cd;
-    D.pts = R.d_pts;
-    D.pt_force = R.d_ptf;
-    D.loads = R.d_loads;
-    D.box = ForceBox{bx0, by0, bz0, bx1 - bx0 + 1, by1 - by0 + 1, bz1 - bz0 + 1, R.d_Fbox};
-    D.Fbox = R.d_Fbox;
-    R.npts = npts;
-    R.on = true;
     return refresh_rotor_table(c);
 }
 
@@ -718,60 +732,70 @@ int lbm_set_turbine(lbm_ctx *c, int id, const lbm_turbine *tb) {
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     RotorHost &R = c->rot[id];
     free_rotor(R);
-    const int np_pol = any_blade ? tb->n_polar : 2;
-    const size_t nb = (size_t)(b1[0] - b0[0] + 1) * (b1[1] - b0[1] + 1) * (b1[2] - b0[2] + 1);
-    R.ptf_len = (size_t)npts * TREE_PT_OUT;
-    bool ok = hipMalloc((void **)&R.d_cl, np_pol * sizeof(float)) == hipSuccess &&
-              hipMalloc((void **)&R.d_cd, np_pol * sizeof(float)) == hipSuccess &&
-              hipMalloc((void **)&R.d_pts, (size_t)npts * PT_STRIDE * sizeof(float)) == hipSuccess &&
-              hipMalloc((void **)&R.d_ptf, R.ptf_len * sizeof(double)) == hipSuccess &&
-              hipMalloc((void **)&R.d_loads, ALM_LOADS_LEN * sizeof(double)) == hipSuccess &&
-              hipMalloc((void **)&R.d_Fbox, nb * 3 * sizeof(float)) == hipSuccess &&
-              hipMalloc((void **)&R.d_nodes, nodes.size() * sizeof(NodeDev)) == hipSuccess &&
-              hipMalloc((void **)&R.d_tpts, pts.size() * sizeof(TreePointDev)) == hipSuccess;
-    if (!ok) {
-        free_rotor(R);
-        return fail(c, LBM_ENOMEM, "turbine buffers");
-    }
-    std::vector<float> cl(np_pol, 0.0f), cd(np_pol, 0.0f);
-    if (any_blade)
-        for (int k = 0; k < np_pol; ++k) {
-            cl[k] = (float)tb->cl[k];
-            cd[k] = (float)tb->cd[k];
+    // on any failure below the slot ends up empty, and the rotor table
+    // must stop naming the freed buffers
+    const int rc = [&]() -> int {
+        const int np_pol = any_blade ? tb->n_polar : 2;
+        const size_t nb = (size_t)(b1[0] - b0[0] + 1) * (b1[1] - b0[1] + 1) * (b1[2] - b0[2] + 1);
+        R.ptf_len = (size_t)npts * TREE_PT_OUT;
+        bool ok = hipMalloc((void **)&R.d_cl, np_pol * sizeof(float)) == hipSuccess &&
+                  hipMalloc((void **)&R.d_cd, np_pol * sizeof(float)) == hipSuccess &&
+                  hipMalloc((void **)&R.d_pts, (size_t)npts * PT_STRIDE * sizeof(float)) == hipSuccess &&
+                  hipMalloc((void **)&R.d_ptf, R.ptf_len * sizeof(double)) == hipSuccess &&
+                  hipMalloc((void **)&R.d_loads, ALM_LOADS_LEN * sizeof(double)) == hipSuccess &&
+                  hipMalloc((void **)&R.d_Fbox, nb * 3 * sizeof(float)) == hipSuccess &&
+                  hipMalloc((void **)&R.d_nodes, nodes.size() * sizeof(NodeDev)) == hipSuccess &&
+                  hipMalloc((void **)&R.d_tpts, pts.size() * sizeof(TreePointDev)) == hipSuccess;
+        if (!ok) {
+            free_rotor(R);
+            return fail(c, LBM_ENOMEM, "turbine buffers");
         }
-    HIPCHK(c, hipMemcpy(R.d_cl, cl.data(), np_pol * sizeof(float), hipMemcpyHostToDevice));
-    HIPCHK(c, hipMemcpy(R.d_cd, cd.data(), np_pol * sizeof(float), hipMemcpyHostToDevice));
-    HIPCHK(c, hipMemcpy(R.d_nodes, nodes.data(), nodes.size() * sizeof(NodeDev), hipMemcpyHostToDevice));
-    HIPCHK(c, hipMemcpy(R.d_tpts, pts.data(), pts.size() * sizeof(TreePointDev), hipMemcpyHostToDevice));
-    HIPCHK(c, hipMemset(R.d_Fbox, 0, nb * 3 * sizeof(float)));
-    HIPCHK(c, hipMemset(R.d_loads, 0, ALM_LOADS_LEN * sizeof(double)));
-    HIPCHK(c, hipMemset(R.d_ptf, 0, R.ptf_len * sizeof(double)));
-    RotorDev &D = R.dev;
-    D = RotorDev{};
-    D.eps = tb->eps;
-    D.radius = tb->radius;
-    D.kernel = tb->kernel;
-    D.half = half;
-    D.npts = npts;
-    D.n_blades = tb->n_blades;
-    D.n_points = 1;
-    D.n_polar = np_pol;
-    D.alpha0 = a0;
-    D.dalpha = da;
-    D.cl = R.d_cl;
-    D.cd = R.d_cd;
-    D.nodes = R.d_nodes;
-    D.n_nodes = tb->n_nodes;
-    D.tpts = R.d_tpts;
-    D.pts = R.d_pts;
-    D.pt_force = R.d_ptf;
-    D.loads = R.d_loads;
-    D.box = ForceBox{b0[0], b0[1], b0[2], b1[0] - b0[0] + 1, b1[1] - b0[1] + 1, b1[2] - b0[2] + 1, R.d_Fbox};
-    D.Fbox = R.d_Fbox;
-    R.npts = npts;
-    R.n_nodes = tb->n_nodes;
-    R.pt_node = pt_node;
-    R.on = true;
+        std::vector<float> cl(np_pol, 0.0f), cd(np_pol, 0.0f);
+        if (any_blade)
+            for (int k = 0; k < np_pol; ++k) {
+                cl[k] = (float)tb->cl[k];
+                cd[k] = (float)tb->cd[k];
+            }
+        HIPCHK(c, hipMemcpy(R.d_cl, cl.data(), np_pol * sizeof(float), hipMemcpyHostToDevice));
+        HIPCHK(c, hipMemcpy(R.d_cd, cd.data(), np_pol * sizeof(float), hipMemcpyHostToDevice));
+        HIPCHK(c, hipMemcpy(R.d_nodes, nodes.data(), nodes.size() * sizeof(NodeDev), hipMemcpyHostToDevice));
+        HIPCHK(c, hipMemcpy(R.d_tpts, pts.data(), pts.size() * sizeof(TreePointDev), hipMemcpyHostToDevice));
+        HIPCHK(c, hipMemset(R.d_Fbox, 0, nb * 3 * sizeof(float)));
+        HIPCHK(c, hipMemset(R.d_loads, 0, ALM_LOADS_LEN * sizeof(double)));
+        HIPCHK(c, hipMemset(R.d_ptf, 0, R.ptf_len * sizeof(double)));
+        RotorDev &D = R.dev;
+        D = RotorDev{};
+        D.eps = tb->eps;
+        D.radius = tb->radius;
+        D.kernel = tb->kernel;
+        D.half = half;
+        D.npts = npts;
+        D.n_blades = tb->n_blades;
+        D.n_points = 1;
+        D.n_polar = np_pol;
+        D.alpha0 = a0;
+        D.dalpha = da;
+        D.cl = R.d_cl;
+        D.cd = R.d_cd;
+        D.nodes = R.d_nodes;
+        D.n_nodes = tb->n_nodes;
+        D.tpts = R.d_tpts;
+        D.pts = R.d_pts;
+        D.pt_force = R.d_ptf;
+        D.loads = R.d_loads;
+        D.box = ForceBox{b0[0], b0[1], b0[2], b1[0] - b0[0] + 1, b1[1] - b0[1] + 1, b1[2] - b0[2] + 1, R.d_Fbox};
+        D.Fbox = R.d_Fbox;
+        R.npts = npts;
+        R.n_nodes = tb->n_nodes;
+        R.pt_node = pt_node;
+        R.on = true;
+        return LBM_OK;
+    }();
+    if (rc != LBM_OK) {
+        free_rotor(R);
+        (void)refresh_rotor_table(c);
+        return rc;
+    }
     return refresh_rotor_table(c);
 }
 
