@@ -201,7 +201,9 @@ int lbm_rotor_loads(lbm_ctx *ctx, int rotor_id, double out[3], double *pt_force)
  *   LBM_FORCE_NONE: points that only sample (probes).
  * Spreading as for rotors (kernel, eps). At most 32 nodes, depth 16, 512
  * points per turbine. A turbine takes one of the 8 rotor slots (set_rotor
- * and set_turbine replace whatever the slot held). The spreading box covers
+ * and set_turbine replace whatever the slot held; arguments are checked
+ * before the slot is touched, and a device error while uploading leaves the
+ * slot empty). The spreading box covers
  * every point's reach over all times (from the rotation and oscillation
  * amplitudes) and must lie inside the domain. All arrays are copied. */
 enum { LBM_NODE_FRAME = 0, LBM_NODE_LINE = 1, LBM_NODE_DISK = 2 };

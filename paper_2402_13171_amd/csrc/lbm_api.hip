@@ -372,10 +372,23 @@ int lbm_set_rotor(lbm_ctx *c, int id, const lbm_rotor *r) {
     if (id < 0 || id >= MAX_ROTORS || !r) return fail(c, LBM_EINVAL, "bad rotor id or null rotor");
     if (r->axis[0] != 1.0 || r->axis[1] != 0.0 || r->axis[2] != 0.0)
         return fail(c, LBM_EINVAL, "rotor axis must be +x");
-    if (r->n_blades < 1 || r->n_points < 1 || r->n_blades * r->n_points > ALM_MAX_POINTS)
+    if (r->n_blades < 1 || r->n_points < 1 || r->n_blades > ALM_MAX_POINTS || r->n_points > ALM_MAX_POINTS ||
+        r->n_blades * r->n_points > ALM_MAX_POINTS)
         return fail(c, LBM_EINVAL, "n_blades*n_points must be in [1, %d]", ALM_MAX_POINTS);
     if (r->n_polar < 2 || !r->r || !r->chord || !r->twist_deg || !r->dl || !r->alpha_deg || !r->cl || !r->cd)
         return fail(c, LBM_EINVAL, "missing rotor arrays");
+    {
+        auto fin = [](const double *a, int n) {
+            for (int k = 0; k < n; ++k)
+                if (!std::isfinite(a[k])) return false;
+            return true;
+        };
+        const double sc[5] = {r->radius, r->omega_rot, r->azimuth0, r->eps, r->pitch_deg};
+        if (!fin(r->hub, 3) || !fin(sc, 5) || !fin(r->r, r->n_points) || !fin(r->chord, r->n_points) ||
+            !fin(r->twist_deg, r->n_points) || !fin(r->dl, r->n_points) || !fin(r->alpha_deg, r->n_polar) ||
+            !fin(r->cl, r->n_polar) || !fin(r->cd, r->n_polar))
+            return fail(c, LBM_EINVAL, "non-finite rotor value");
+    }
     if (r->kernel != LBM_KERNEL_GAUSS && r->kernel != LBM_KERNEL_ROMA3)
         return fail(c, LBM_EINVAL, "unknown spreading kernel %d", r->kernel);
     if (r->tip_loss != 0 && r->tip_loss != 1) return fail(c, LBM_EINVAL, "tip_loss must be 0 or 1");
@@ -578,6 +591,12 @@ void point_reach(const lbm_turbine *tb, const std::vector<HostPose> &P, int node
 
 bool unit(const double *a) { return std::fabs(h_norm(a) - 1.0) < 1e-9; }
 
+bool all_finite(const double *a, int n) {
+    for (int k = 0; k < n; ++k)
+        if (!std::isfinite(a[k])) return false;
+    return true;
+}
+
 }  // namespace
 
 int lbm_set_turbine(lbm_ctx *c, int id, const lbm_turbine *tb) {
@@ -587,12 +606,18 @@ int lbm_set_turbine(lbm_ctx *c, int id, const lbm_turbine *tb) {
         return fail(c, LBM_EINVAL, "n_nodes must be in [1, %d]", TREE_MAX_NODES);
     if (tb->kernel != LBM_KERNEL_GAUSS && tb->kernel != LBM_KERNEL_ROMA3)
         return fail(c, LBM_EINVAL, "unknown spreading kernel %d", tb->kernel);
-    if (tb->kernel == LBM_KERNEL_GAUSS && !(tb->eps > 0.0)) return fail(c, LBM_EINVAL, "eps must be positive");
+    if (tb->kernel == LBM_KERNEL_GAUSS && !(tb->eps > 0.0 && std::isfinite(tb->eps)))
+        return fail(c, LBM_EINVAL, "eps must be positive");
+    if (!std::isfinite(tb->radius)) return fail(c, LBM_EINVAL, "non-finite radius");
     bool any_blade = false;
     int npts = 0;
     for (int k = 0; k < tb->n_nodes; ++k) {
         const lbm_node &N = tb->nodes[k];
         if (N.parent < -1 || N.parent >= k) return fail(c, LBM_EINVAL, "node %d: parent must precede it", k);
+        const double motion[9] = {N.omega, N.angle0, N.amp, N.freq, N.phase, N.coef, N.pitch_deg, 0.0, 0.0};
+        if (!all_finite(N.pos, 3) || !all_finite(N.rot, 9) || !all_finite(N.axis, 3) || !all_finite(N.disp, 3) ||
+            !all_finite(N.dir, 3) || !all_finite(N.normal, 3) || !all_finite(motion, 9))
+            return fail(c, LBM_EINVAL, "node %d: non-finite value", k);
         int depth = 1;
         for (int q = N.parent; q >= 0; q = tb->nodes[q].parent) ++depth;
         if (depth > TREE_MAX_DEPTH) return fail(c, LBM_EINVAL, "node %d: tree deeper than %d", k, TREE_MAX_DEPTH);
@@ -618,6 +643,9 @@ int lbm_set_turbine(lbm_ctx *c, int id, const lbm_turbine *tb) {
             continue;
         }
         if (N.n_points < 1 || !N.s || !N.width) return fail(c, LBM_EINVAL, "node %d: needs n_points, s, width", k);
+        if (!all_finite(N.s, N.n_points) || !all_finite(N.width, N.n_points) || (N.chord && !all_finite(N.chord, N.n_points)) ||
+            (N.twist && !all_finite(N.twist, N.n_points)))
+            return fail(c, LBM_EINVAL, "node %d: non-finite point data", k);
         if (N.kind == LBM_NODE_DISK && N.n_azimuth < 1) return fail(c, LBM_EINVAL, "node %d: n_azimuth < 1", k);
         if (N.kind == LBM_NODE_LINE && !unit(N.dir)) return fail(c, LBM_EINVAL, "node %d: dir must be a unit vector", k);
         if (N.force == LBM_FORCE_BLADE) {
@@ -644,6 +672,8 @@ int lbm_set_turbine(lbm_ctx *c, int id, const lbm_turbine *tb) {
     double a0 = 0.0, da = 1.0;
     if (any_blade) {
         if (tb->n_polar < 2 || !tb->alpha_deg || !tb->cl || !tb->cd) return fail(c, LBM_EINVAL, "missing polars");
+        if (!all_finite(tb->alpha_deg, tb->n_polar) || !all_finite(tb->cl, tb->n_polar) || !all_finite(tb->cd, tb->n_polar))
+            return fail(c, LBM_EINVAL, "non-finite polar value");
         a0 = tb->alpha_deg[0];
         da = (tb->alpha_deg[tb->n_polar - 1] - a0) / (tb->n_polar - 1);
         if (!(da > 0.0)) return fail(c, LBM_EINVAL, "polar angles must ascend");

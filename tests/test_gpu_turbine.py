@@ -226,4 +226,13 @@ def test_turbine_argument_validation():
                                                                    width=np.ones(600),
                                                                    chord=np.ones(600),
                                                                    twist=np.zeros(600)))
+    bad(lambda t: t["nodes"][0].update(pos=(np.nan, 16.0, 16.0)))  # non-finite pose
+    bad(lambda t: t["nodes"][1].update(chord=np.full(8, np.inf)))    # non-finite point data
     sim.set_turbine(0, good)  # and the good one is accepted
+    # arguments are checked before the slot is touched: a rejected call
+    # leaves the earlier turbine in place
+    bad(lambda t: t["nodes"][1].update(parent=1))
+    sim.init_tgv(u0=0.01)
+    sim.step(2)
+    nl, pts = sim.turbine_loads(0)
+    assert pts.shape == (24, 9) and np.isfinite(nl).all() and np.abs(pts[:, 6:9]).max() > 0
