@@ -110,6 +110,25 @@ def test_single_turbine_full_size_first_steps():
     assert T > 0 and Q > 0  # the rotor is driven by the wind and thrusts downstream
 
 
+def test_single_turbine_200_steps():
+    """The single-turbine case for 200 steps (the rotor turns 250 degrees):
+    fields within 1e-4 of the largest velocity and thrust, torque and power
+    within 1e-3 of the largest load, every step."""
+    _need_gpu()
+    rot = workloads.single_turbine_rotor()
+    print("single turbine, 200 steps (FP64 oracle on the host: ~25 s)", flush=True)
+    sim, ref, hist = run_pair((256, 128, 128), [rot], 200, bc_x="inout", u_in=(0.05, 0, 0), omega=1.9)
+    lg = np.array([h[2] for h in hist])
+    lr = np.array([h[3] for h in hist])
+    lerr = (np.abs(lg - lr) / np.abs(lr).max(axis=0)).max()
+    _, ug = sim.fields()
+    _, ur = ref.fields()
+    err = np.linalg.norm(ug - ur, axis=0).max() / np.linalg.norm(ur, axis=0).max()
+    print(f"single turbine 200 steps: worst load error {lerr:.2e}, field eps_max {err:.2e}")
+    assert lerr <= 1e-3
+    assert err <= 1e-4
+
+
 def _closure_blob(seed=10):
     from oracle import mlp_ref
     rng = np.random.default_rng(seed)
