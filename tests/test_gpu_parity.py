@@ -53,16 +53,23 @@ def test_tgv64_fp32_matches_oracle_after_50_steps():
     ref.init_fields(rho0, u0)
     m0 = sim.global_moments()[0]
     assert m0 == pytest.approx(n ** 3, rel=1e-10)  # FP32-stored deviations of an FP64 init
+    pmax = 0.0
     for s in range(50):
         sim.step(1)
         m, p, e = sim.global_moments()
         assert abs(m - m0) <= 1e-9 * m0, s
-        assert np.abs(p).max() <= 1e-6 * n ** 3 * 0.05, s
+        pmax = max(pmax, np.abs(p).max())
+    # the TGV carries no net momentum; what the GPU shows is the rounding of
+    # the FP32-stored deviations (|d| <~ 0.02, half an ulp ~6e-10 each), a
+    # random walk over 27 N populations and 50 steps: sqrt(27 N 50) 6e-10
+    # ~ 1.1e-5 = 8.6e-10 N u0 (measured 8.1e-6); the FP64 oracle stays
+    # below 1e-10 N u0
+    assert pmax <= 1e-9 * n ** 3 * 0.05, pmax
     ref.step(50)
     _, u = sim.fields()
     _, ur = ref.fields()
     err = rel_vel_err(u, ur)
-    print(f"tgv64 fp32 50 steps: eps_max = {err:.3e}")
+    print(f"tgv64 fp32 50 steps: eps_max = {err:.3e}, max |P| = {pmax:.2e} (N u0 = {n ** 3 * 0.05:.0f})")
     assert err <= 1e-5
 
 
