@@ -132,6 +132,50 @@ def train(feats, targets, blob0, epochs=8, batch=4096, lr=2e-3, seed=0, log=prin
     return blob, losses
 
 
+def training_throughput(batches=(4096, 65536), iters=200, seed=0, log=print):
+    """Samples per second of one training iteration (forward + backward on
+    the device, loss and gradient, then one Adam update) and of inference,
+    on seeded synthetic features (the kernels' cost does not depend on the
+    values), timed with HIP events on the trainer's stream."""
+    import torch
+    rng = np.random.default_rng(seed)
+    feats = rng.standard_normal((max(batches), 6))
+    targets = np.abs(rng.standard_normal(max(batches)))
+    tr = MlpTrainer(make_initial_blob(feats, targets, seed))
+    F = torch.from_numpy(feats.astype(np.float32)).cuda()
+    Y = torch.from_numpy((targets / np.sqrt(np.mean(targets ** 2))).astype(np.float32)).cuda()
+    out = {}
+    for b in batches:
+        fb, yb = F[:b].contiguous(), Y[:b].contiguous()
+        for _ in range(10):
+            tr.loss_grad(fb, yb)
+            tr.adam_step()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(tr.stream)
+        for _ in range(iters):
+            tr.loss_grad(fb, yb)
+            tr.adam_step()
+        e1.record(tr.stream)
+        torch.cuda.synchronize()
+        ms_train = e0.elapsed_time(e1) / iters
+        tr.forward(fb)
+        torch.cuda.synchronize()
+        e0.record(tr.stream)
+        for _ in range(iters):
+            tr.forward(fb)
+        e1.record(tr.stream)
+        torch.cuda.synchronize()
+        ms_inf = e0.elapsed_time(e1) / iters
+        out[str(b)] = {"train_ms_per_iteration": ms_train, "train_samples_per_s": b / (ms_train * 1e-3),
+                       "inference_ms": ms_inf, "inference_samples_per_s": b / (ms_inf * 1e-3)}
+        log(f"closure training batch {b}: {b / (ms_train * 1e-3):.3e} samples/s "
+            f"({ms_train * 1e3:.1f} us per iteration), inference {b / (ms_inf * 1e-3):.3e} samples/s")
+    tr.take_loss()
+    tr.close()
+    return out
+
+
 def make_initial_blob(feats, targets, seed=0):
     """He-initialised network with the training set's feature statistics and
     the target rms as output scale."""
