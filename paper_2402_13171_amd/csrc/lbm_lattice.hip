@@ -164,9 +164,55 @@ __device__ __forceinline__ void open_x_sources(const Geo &g, int x, int y, int z
 // and x = nx-1 lanes from outside the box are replaced by the inlet
 // equilibrium and the ghost plane, their pushes out of the box dropped, and
 // the slots no fluid cell pushes filled (odd_boundary_extras).
-template <typename T, int PAR, int CL, bool BCG, bool FRC, bool GR, bool XO = false>
+// Odd-step stores of the 18 x-shifted directions through LDS. Pushed
+// directly, every wave's store of direction i (c_x = +-1) starts one element
+// off a cache line, so each line is written by two waves, and a part of the
+// lines reaches HBM twice (3-8 % more write traffic than the algorithmic
+// bytes). Here each lane first puts its value in LDS, then lane t stores the
+// value aimed at its own x (aligned whole lines per wave): for c_x = -1
+// lanes 0..254 take the pushes of lanes 1..255 and lane 255 stores lane 0's
+// push to x0 - 1; for c_x = +1 lanes 1..255 take lanes 0..254 and lane 0
+// stores lane 255's push to x0 + 256 (x0: the tile's first x, wrapped
+// periodically). The same slots and values as the direct pushes, one store
+// per lane and direction. In an open domain the pushes out of the box at x = 0
+// and x = nx-1 are dropped. Needs one x-row tile of 256 valid lanes (tw = 256,
+// nx a multiple of 256). stage: [18][258] of T.
+constexpr int STAGE_W = 258;
+// the launch chooses the staged kernels when the tiles allow it
+static bool odd_staged_ok(const Geo &g, unsigned tw_log2) { return tw_log2 == 8u && (g.nx % 256) == 0; }
+template <typename T, bool XO>
+__device__ __forceinline__ void write_odd_staged(const Geo &g, const uint32_t *xs, const uint32_t *rows,
+                                                 const float *o, T *stage) {
+    const uint32_t t = threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+        Store<T>::st(stage + j * STAGE_W + t, o[3 * j]);                // c_x = -1, source lane t
+        Store<T>::st(stage + (9 + j) * STAGE_W + t + 2, o[3 * j + 2]);  // c_x = +1, source lane t
+    }
+    Unroll32<T, 0>::template write_periodic_cx<0>(g, xs, rows, o);
+    __syncthreads();
+    const uint32_t nx = (uint32_t)g.nx, x = xs[1], x0 = x - t;
+    const uint32_t x_lo = x0 == 0u ? nx - 1u : x0 - 1u;      // x0 - 1, wrapped
+    const uint32_t x_hi = x0 + 256u == nx ? 0u : x0 + 256u;  // x0 + 256, wrapped
+    const bool last = t == 255u, first = t == 0u;
+    const uint32_t xm = last ? x_lo : x, im = last ? 0u : t + 1u;     // c_x = -1
+    const uint32_t xp = first ? x_hi : x, ip = first ? 257u : t + 1u;  // c_x = +1
+    const bool keep_m = !(XO && last && x0 == 0u), keep_p = !(XO && first && x0 + 256u == nx);
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+        // directions 3j (c_x = -1) and 3j + 2 (c_x = +1) share c_y, c_z: row rows[j]
+        const uint32_t r = rows[j];
+        const char *pm = (const char *)g.pops + (size_t)(3 * j) * g.P * sizeof(T);
+        const char *pp = (const char *)g.pops + (size_t)(3 * j + 2) * g.P * sizeof(T);
+        const T vm = stage[j * STAGE_W + im], vp = stage[(9 + j) * STAGE_W + ip];
+        if (keep_m) *(T *)(pm + (r + xm) * (uint32_t)sizeof(T)) = vm;
+        if (keep_p) *(T *)(pp + (r + xp) * (uint32_t)sizeof(T)) = vp;
+    }
+}
+
+template <typename T, int PAR, int CL, bool BCG, bool FRC, bool GR, bool XO = false, bool LS = false>
 __device__ __forceinline__ void cell_update(const Geo &g, const Physics &ph, int x, int y, int z, bool valid,
-                                            MlpLds &mlp_lds) {
+                                            MlpLds &mlp_lds, T *stage = nullptr) {
     if (CL != CL_MLP && !valid) return;
     const size_t cell = cidx(g, x, y, z);
     // fast path (no boundary rules): 32-bit offsets, see Unroll32
@@ -232,7 +278,10 @@ __device__ __forceinline__ void cell_update(const Geo &g, const Physics &ph, int
                 Store<T>::st(G + (size_t)(J / 3) * g.ny * g.nz + y + (size_t)g.ny * z, o[J]);
         }
     } else if (!BCG) {
-        if (XO) {
+        if constexpr (LS) {
+            write_odd_staged<T, XO>(gw, xs, rows, o, stage);
+            if (XO) odd_boundary_extras<T>(g, x, y, z, o);
+        } else if (XO) {
             // pushes out of the box through x are dropped
             if (x != 0) Unroll32<T, 0>::template write_periodic_cx<-1>(gw, xs, rows, o);
             Unroll32<T, 0>::template write_periodic_cx<0>(gw, xs, rows, o);
@@ -248,7 +297,11 @@ __device__ __forceinline__ void cell_update(const Geo &g, const Physics &ph, int
 }
 
 
-template <typename T, int PAR, int CL, bool BCG, bool FRC, bool GR, bool XO = false>
+// LS: odd-step stores staged through LDS (write_odd_staged); the launch picks
+// it for odd steps on the fast path without the learned closure when the tiles
+// are whole 256-lane rows (the closure variant, bound by its arithmetic,
+// measured slower with the extra barrier).
+template <typename T, int PAR, int CL, bool BCG, bool FRC, bool GR, bool XO = false, bool LS = false>
 __global__ __launch_bounds__(256) void k_stream_collide(Geo g, Physics ph, unsigned gx, unsigned gy, unsigned total,
                                                         unsigned tw_log2) {
     const unsigned tile = xcd_tile(blockIdx.x, total);
@@ -266,7 +319,13 @@ __global__ __launch_bounds__(256) void k_stream_collide(Geo g, Physics ph, unsig
     // network operands: DMA into LDS now, in flight with the population loads
     __shared__ MlpLds mlp_lds;
     if (CL == CL_MLP) mlp_stage_lds(ph.mlp, &mlp_lds);
-    cell_update<T, PAR, CL, BCG, FRC, GR, XO>(g, ph, x, y, z, valid, mlp_lds);
+    if constexpr (LS) {
+        static_assert(PAR == 1 && !BCG && CL != CL_MLP, "staged stores: fast-path odd steps without the closure");
+        __shared__ T stage[18 * STAGE_W];
+        cell_update<T, PAR, CL, BCG, FRC, GR, XO, true>(g, ph, x, y, z, valid, mlp_lds, stage);
+    } else {
+        cell_update<T, PAR, CL, BCG, FRC, GR, XO>(g, ph, x, y, z, valid, mlp_lds);
+    }
 }
 
 // Odd step on the z wall planes (z = 0 and / or nz-1, all x and y) with the
@@ -292,7 +351,7 @@ __global__ __launch_bounds__(256) void k_stream_collide_walls(Geo g, Physics ph,
 // goes back to the slot the collision would write, so the store keeps its
 // content up to a permutation). Its rate is the achievable-bandwidth ceiling
 // of the stream-collide access pattern.
-template <typename T, int PAR>
+template <typename T, int PAR, bool LS = false>
 __global__ __launch_bounds__(256) void k_pattern_probe(Geo g, unsigned gx, unsigned gy, unsigned total,
                                                        unsigned tw_log2) {
     const unsigned tile = xcd_tile(blockIdx.x, total);
@@ -310,7 +369,12 @@ __global__ __launch_bounds__(256) void k_pattern_probe(Geo g, unsigned gx, unsig
         uint32_t xs[3], rows[9];
         periodic_offsets(g, x, y, z, xs, rows);
         Unroll32<T, 0>::read_periodic(g, xs, rows, d);
-        Unroll32<T, 0>::write_periodic(g, xs, rows, d);
+        if constexpr (LS) {
+            __shared__ T stage[18 * STAGE_W];
+            write_odd_staged<T, false>(g, xs, rows, d, stage);
+        } else {
+            Unroll32<T, 0>::write_periodic(g, xs, rows, d);
+        }
     }
 }
 
@@ -319,46 +383,71 @@ int launch_pattern_probe(int storage, int parity, const Geo &g, hipStream_t s) {
     const unsigned tw = 1u << twl, th = 256u >> twl;
     const unsigned gx = (g.nx + tw - 1) / tw, gy = (g.ny + th - 1) / th, total = gx * gy * (unsigned)g.nz;
     const dim3 grd(total, 1, 1), blk(256, 1, 1);
+    // the odd pass stores like the staged stream-collide kernels where those run
+    const bool ls = odd_staged_ok(g, twl);
     switch (storage * 2 + parity) {
         case 0: k_pattern_probe<float, 0><<<grd, blk, 0, s>>>(g, gx, gy, total, twl); break;
-        case 1: k_pattern_probe<float, 1><<<grd, blk, 0, s>>>(g, gx, gy, total, twl); break;
+        case 1:
+            if (ls) k_pattern_probe<float, 1, true><<<grd, blk, 0, s>>>(g, gx, gy, total, twl);
+            else k_pattern_probe<float, 1><<<grd, blk, 0, s>>>(g, gx, gy, total, twl);
+            break;
         case 2: k_pattern_probe<__half, 0><<<grd, blk, 0, s>>>(g, gx, gy, total, twl); break;
-        case 3: k_pattern_probe<__half, 1><<<grd, blk, 0, s>>>(g, gx, gy, total, twl); break;
+        case 3:
+            if (ls) k_pattern_probe<__half, 1, true><<<grd, blk, 0, s>>>(g, gx, gy, total, twl);
+            else k_pattern_probe<__half, 1><<<grd, blk, 0, s>>>(g, gx, gy, total, twl);
+            break;
         case 4: k_pattern_probe<bf16_t, 0><<<grd, blk, 0, s>>>(g, gx, gy, total, twl); break;
-        case 5: k_pattern_probe<bf16_t, 1><<<grd, blk, 0, s>>>(g, gx, gy, total, twl); break;
+        case 5:
+            if (ls) k_pattern_probe<bf16_t, 1, true><<<grd, blk, 0, s>>>(g, gx, gy, total, twl);
+            else k_pattern_probe<bf16_t, 1><<<grd, blk, 0, s>>>(g, gx, gy, total, twl);
+            break;
         default: return -1;
     }
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
 // ------------------------------------------------------------ dispatch
+// one stream-collide launch; staged odd-step stores where they apply
+template <typename T, int PAR, int CL, bool BCG, bool FRC, bool GR, bool XO = false>
+static void launch_k1(bool ls, dim3 grd, dim3 blk, hipStream_t s, const Geo &g, const Physics &ph, unsigned gx,
+                      unsigned gy, unsigned total, unsigned twl) {
+    if constexpr (PAR == 1 && !BCG && CL != CL_MLP) {
+        if (ls) {
+            k_stream_collide<T, PAR, CL, BCG, FRC, GR, XO, true><<<grd, blk, 0, s>>>(g, ph, gx, gy, total, twl);
+            return;
+        }
+    }
+    k_stream_collide<T, PAR, CL, BCG, FRC, GR, XO><<<grd, blk, 0, s>>>(g, ph, gx, gy, total, twl);
+}
+
 template <typename T, int PAR, int CL>
 static void launch_sc(int mode, bool frc, bool gr, const Geo &g, const Physics &ph, hipStream_t s) {
     const unsigned twl = g.nx >= 256 ? 8u : (g.nx >= 128 ? 7u : 6u);
     const unsigned tw = 1u << twl, th = 256u >> twl;
     const unsigned gx = (g.nx + tw - 1) / tw, gy = (g.ny + th - 1) / th, total = gx * gy * (unsigned)g.nz;
     dim3 blk(256, 1, 1), grd(total, 1, 1);
+    const bool ls = odd_staged_ok(g, twl);
     // general rates only on the general-boundary path (periodic boxes included)
     if (gr) {
-        if (frc) k_stream_collide<T, PAR, CL, true, true, true><<<grd, blk, 0, s>>>(g, ph, gx, gy, total, twl);
-        else k_stream_collide<T, PAR, CL, true, false, true><<<grd, blk, 0, s>>>(g, ph, gx, gy, total, twl);
+        if (frc) launch_k1<T, PAR, CL, true, true, true>(ls, grd, blk, s, g, ph, gx, gy, total, twl);
+        else launch_k1<T, PAR, CL, true, false, true>(ls, grd, blk, s, g, ph, gx, gy, total, twl);
     } else if (mode == SC_GENERAL) {
-        if (frc) k_stream_collide<T, PAR, CL, true, true, false><<<grd, blk, 0, s>>>(g, ph, gx, gy, total, twl);
-        else k_stream_collide<T, PAR, CL, true, false, false><<<grd, blk, 0, s>>>(g, ph, gx, gy, total, twl);
+        if (frc) launch_k1<T, PAR, CL, true, true, false>(ls, grd, blk, s, g, ph, gx, gy, total, twl);
+        else launch_k1<T, PAR, CL, true, false, false>(ls, grd, blk, s, g, ph, gx, gy, total, twl);
     } else if (mode == SC_SPLIT && PAR == 0) {
         // even step of an open domain: cell-local, the z walls play no part;
         // only the x = nx-1 lanes add the outflow ghost plane
         const bool xo = g.bc_x == BC_INOUT;
         if (frc) {
-            if (xo) k_stream_collide<T, PAR, CL, false, true, false, true><<<grd, blk, 0, s>>>(g, ph, gx, gy, total, twl);
-            else k_stream_collide<T, PAR, CL, false, true, false><<<grd, blk, 0, s>>>(g, ph, gx, gy, total, twl);
+            if (xo) launch_k1<T, PAR, CL, false, true, false, true>(ls, grd, blk, s, g, ph, gx, gy, total, twl);
+            else launch_k1<T, PAR, CL, false, true, false>(ls, grd, blk, s, g, ph, gx, gy, total, twl);
         } else {
-            if (xo) k_stream_collide<T, PAR, CL, false, false, false, true><<<grd, blk, 0, s>>>(g, ph, gx, gy, total, twl);
-            else k_stream_collide<T, PAR, CL, false, false, false><<<grd, blk, 0, s>>>(g, ph, gx, gy, total, twl);
+            if (xo) launch_k1<T, PAR, CL, false, false, false, true>(ls, grd, blk, s, g, ph, gx, gy, total, twl);
+            else launch_k1<T, PAR, CL, false, false, false>(ls, grd, blk, s, g, ph, gx, gy, total, twl);
         }
     } else if (mode == SC_FAST) {
-        if (frc) k_stream_collide<T, PAR, CL, false, true, false><<<grd, blk, 0, s>>>(g, ph, gx, gy, total, twl);
-        else k_stream_collide<T, PAR, CL, false, false, false><<<grd, blk, 0, s>>>(g, ph, gx, gy, total, twl);
+        if (frc) launch_k1<T, PAR, CL, false, true, false>(ls, grd, blk, s, g, ph, gx, gy, total, twl);
+        else launch_k1<T, PAR, CL, false, false, false>(ls, grd, blk, s, g, ph, gx, gy, total, twl);
     } else if constexpr (PAR == 1) {
         // odd step of an open domain: every cell off the z walls on the fast
         // path, the x inflow/outflow rules applied per lane; then the wall
@@ -368,11 +457,11 @@ static void launch_sc(int mode, bool frc, bool gr, const Geo &g, const Physics &
         gi.skip_zhi = g.bc_zhi != BC_PERIODIC;
         const bool xo = g.bc_x == BC_INOUT;
         if (frc) {
-            if (xo) k_stream_collide<T, PAR, CL, false, true, false, true><<<grd, blk, 0, s>>>(gi, ph, gx, gy, total, twl);
-            else k_stream_collide<T, PAR, CL, false, true, false><<<grd, blk, 0, s>>>(gi, ph, gx, gy, total, twl);
+            if (xo) launch_k1<T, PAR, CL, false, true, false, true>(ls, grd, blk, s, gi, ph, gx, gy, total, twl);
+            else launch_k1<T, PAR, CL, false, true, false>(ls, grd, blk, s, gi, ph, gx, gy, total, twl);
         } else {
-            if (xo) k_stream_collide<T, PAR, CL, false, false, false, true><<<grd, blk, 0, s>>>(gi, ph, gx, gy, total, twl);
-            else k_stream_collide<T, PAR, CL, false, false, false><<<grd, blk, 0, s>>>(gi, ph, gx, gy, total, twl);
+            if (xo) launch_k1<T, PAR, CL, false, false, false, true>(ls, grd, blk, s, gi, ph, gx, gy, total, twl);
+            else launch_k1<T, PAR, CL, false, false, false>(ls, grd, blk, s, gi, ph, gx, gy, total, twl);
         }
         const unsigned nxy = (unsigned)g.nx * (unsigned)g.ny;
         const unsigned nlo = gi.skip_zlo ? nxy : 0u, nhi = gi.skip_zhi ? nxy : 0u;

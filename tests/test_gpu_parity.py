@@ -120,6 +120,34 @@ def test_boundaries_match_oracle(case, steps, general_path):
     assert err <= 2e-7 * steps, (case, err)
 
 
+@pytest.mark.parametrize("case", [
+    dict(nx=256, storage="f32"),
+    dict(nx=512, storage="f16"),
+    dict(nx=256, storage="bf16", body_force=(2e-5, -1e-5, 0.0)),
+    dict(nx=256, storage="f32", bc_x="inout", bc_z=("noslip", "freeslip"), u_in=(0.05, 0.0, 0.0)),
+    dict(nx=256, storage="f16", bc_x="inout", bc_z=("periodic", "periodic"), u_in=(0.04, 0.01, 0.0)),
+], ids=["f32-periodic", "f16-periodic-2tiles", "bf16-forced", "f32-open-walls", "f16-open"])
+@pytest.mark.parametrize("steps", [1, 2, 5])
+def test_wide_rows_odd_step_whole_line_stores(case, steps):
+    """Rows whose length is a multiple of 256 take the odd-step stores staged
+    through LDS (every lane stores the value aimed at its own x; the tile-edge
+    pushes by the end lanes, dropped at x = 0 / nx-1 in an open domain):
+    populations against the oracle after even and odd step counts."""
+    _need_gpu()
+    case = dict(case)
+    nx, storage = case.pop("nx"), case.pop("storage")
+    ny, nz = 6, 5
+    sim, ref = make_pair(nx, ny, nz, omega=1.7, storage=storage, **case)
+    rho, u = random_field(nx, ny, nz, seed=20 + steps)
+    sim.init_fields(rho, u)
+    ref.init_fields(rho, u)
+    sim.step(steps)
+    ref.step(steps)
+    err = np.abs(sim.pops() - ref.get_pops()).max()
+    tol = {"f32": 2e-7, "f16": 4e-5, "bf16": 4e-4}[storage] * steps
+    assert err <= tol, (case, err)
+
+
 def test_dense_force_field_kolmogorov_step():
     _need_gpu()
     n = 16
