@@ -129,9 +129,10 @@ def test_boundaries_match_oracle(case, steps, general_path):
 ], ids=["f32-periodic", "f16-periodic-2tiles", "bf16-forced", "f32-open-walls", "f16-open"])
 @pytest.mark.parametrize("steps", [1, 2, 5])
 def test_wide_rows_odd_step_whole_line_stores(case, steps):
-    """Rows whose length is a multiple of 256 take the odd-step stores staged
-    through LDS (every lane stores the value aimed at its own x; the tile-edge
-    pushes by the end lanes, dropped at x = 0 / nx-1 in an open domain):
+    """Rows whose length is a multiple of 256: 16-bit storage takes the
+    odd-step stores staged through LDS (every lane stores the value aimed at
+    its own x; the tile-edge pushes by the end lanes, dropped at x = 0 / nx-1
+    in an open domain), FP32 the direct pushes on the same 256-lane tiles:
     populations against the oracle after even and odd step counts."""
     _need_gpu()
     case = dict(case)
