@@ -334,7 +334,18 @@ __global__ __launch_bounds__(ALM_BLOCK) void k_alm_points(Geo g, Physics ph, Rot
 constexpr int SP_TX = 16, SP_TY = 4, SP_TZ = 4;
 static_assert(SP_TX * SP_TY * SP_TZ == ALM_BLOCK, "one cell per thread");
 
-__global__ __launch_bounds__(ALM_BLOCK) void k_alm_spread(const RotorDev *rots, int rid, int tiles_x, int tiles_y) {
+// One launch spreads every slot: workgroups [first[r], first[r+1]) take the
+// tiles of slot r (tile counts per axis in tiles[r]).
+struct SpreadTiles {
+    int nslots;
+    int first[MAX_ROTORS + 1];
+    int tx[MAX_ROTORS], ty[MAX_ROTORS];
+};
+
+__global__ __launch_bounds__(ALM_BLOCK) void k_alm_spread(const RotorDev *rots, SpreadTiles st) {
+    int rid = 0;
+    while (rid + 1 < st.nslots && (int)blockIdx.x >= st.first[rid + 1]) ++rid;  // uniform per workgroup
+    const int blk = (int)blockIdx.x - st.first[rid], tiles_x = st.tx[rid], tiles_y = st.ty[rid];
     const RotorDev &R = rots[rid];
     const int npts = R.npts;
     const ForceBox &B = R.box;
@@ -342,7 +353,7 @@ __global__ __launch_bounds__(ALM_BLOCK) void k_alm_spread(const RotorDev *rots, 
     __shared__ float sp[ALM_MAX_PTS * PT_STRIDE];
     __shared__ int s_idx[ALM_MAX_PTS];
     __shared__ int s_wave[ALM_BLOCK / 64];
-    const int tx = blockIdx.x % tiles_x, ty = (blockIdx.x / tiles_x) % tiles_y, tz = blockIdx.x / (tiles_x * tiles_y);
+    const int tx = blk % tiles_x, ty = (blk / tiles_x) % tiles_y, tz = blk / (tiles_x * tiles_y);
     // tile extent in lattice coordinates (clipped to the box)
     const int X0 = B.x0 + tx * SP_TX, Y0 = B.y0 + ty * SP_TY, Z0 = B.z0 + tz * SP_TZ;
     const int X1 = min(X0 + SP_TX, B.x0 + B.bnx) - 1, Y1 = min(Y0 + SP_TY, B.y0 + B.bny) - 1,
@@ -403,11 +414,16 @@ static void alm_t(const Geo &g, const Physics &ph, const RotorDev *h_rots, Rotor
         nb = b > nb ? b : nb;
     }
     k_alm_points<T, PAR><<<dim3(nb, nrot), ALM_BLOCK, 0, s>>>(g, ph, d_rots, t);
+    SpreadTiles st{};
+    st.nslots = nrot;
     for (int r = 0; r < nrot; ++r) {
         const ForceBox &B = h_rots[r].box;
         const int tx = (B.bnx + SP_TX - 1) / SP_TX, ty = (B.bny + SP_TY - 1) / SP_TY, tz = (B.bnz + SP_TZ - 1) / SP_TZ;
-        k_alm_spread<<<(unsigned)(tx * ty * tz), ALM_BLOCK, 0, s>>>(d_rots, r, tx, ty);
+        st.tx[r] = tx;
+        st.ty[r] = ty;
+        st.first[r + 1] = st.first[r] + tx * ty * tz;
     }
+    k_alm_spread<<<(unsigned)st.first[nrot], ALM_BLOCK, 0, s>>>(d_rots, st);
 }
 
 int launch_alm(int storage, int parity, const Geo &g, const Physics &ph, const RotorDev *h_rots, RotorDev *d_rots,

@@ -236,3 +236,37 @@ def test_turbine_argument_validation():
     sim.step(2)
     nl, pts = sim.turbine_loads(0)
     assert pts.shape == (24, 9) and np.isfinite(nl).all() and np.abs(pts[:, 6:9]).max() > 0
+
+
+def test_rotors_and_a_turbine_in_one_box():
+    """Two rotor slots and a turbine-tree slot in one periodic box (one
+    spreading launch covers every slot's box): per-slot loads and the flow
+    against the oracle."""
+    _need_gpu()
+    from paper_2402_13171_amd.lbm import Lbm
+    shape = (64, 48, 48)
+    ra = _rotor((14.0, 23.5, 24.0), R=6.0)
+    rb = _rotor((52.0, 23.5, 24.0), R=6.0, kernel="roma3", azimuth0=1.0)
+    disk = TB.actuator_disk((34.0, 24.0, 24.0), radius=6.0, n_rings=3, n_azimuth=12)
+    sim = Lbm(*shape, omega=1.8)
+    ref = oracle.Grid(*shape, omega=1.8)
+    rho, u = _uniform(shape)
+    sim.init_fields(rho, u)
+    ref.init_fields(rho, u)
+    for g in (sim, ref):
+        g.set_rotor(0, ra)
+        g.set_turbine(1, disk)
+        g.set_rotor(2, rb)
+    worst = 0.0
+    for s in range(8):
+        sim.step(1)
+        ref.step(1)
+        for rid in (0, 2):
+            lg, lr = sim.rotor_loads(rid), ref.rotor_loads(rid)
+            worst = max(worst, np.abs(lg - lr).max() / np.abs(lr).max())
+        nlg, _ = sim.turbine_loads(1)
+        nlr, _ = ref.turbine_loads(1)
+        worst = max(worst, np.abs(nlg[:, 0] - nlr[:, 0]).max() / np.abs(nlr[:, 0]).max())
+    e = check_fields(sim, ref, 1e-5)
+    print(f"two rotors + a disk: worst load error {worst:.2e}, field {e:.2e}")
+    assert worst <= 2e-5
