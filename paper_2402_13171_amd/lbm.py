@@ -356,14 +356,18 @@ class Lbm:
     def turbine_loads(self, tid):
         """(node_loads[n_nodes][7]: force, moment about the node origin,
         power; points[npts][9]: x, v, F) of the last step."""
+        if not isinstance(self._npts.get(tid), tuple):
+            raise LbmError(EINVAL, f"slot {tid} holds no turbine tree")
         _, nn, npts = self._npts[tid]
         nl, pts = np.zeros((nn, 7)), np.zeros((npts, 9))
         self._check(lib().lbm_turbine_loads(self._ctx, tid, _p(nl), _p(pts)))
         return nl, pts
 
     def rotor_loads(self, rid, with_points=False):
+        if isinstance(self._npts.get(rid), tuple):
+            raise LbmError(EINVAL, f"slot {rid} holds a turbine tree: use turbine_loads")
         out = np.zeros(3)
-        pf = np.zeros((self._npts[rid], 3))
+        pf = np.zeros((self._npts.get(rid, 0), 3))
         self._check(lib().lbm_rotor_loads(self._ctx, rid, _p(out), _p(pf)))
         return (out, pf) if with_points else out
 
