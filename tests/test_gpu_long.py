@@ -1,7 +1,8 @@
 """Long GPU <-> oracle runs, opt-in (set LBM_LONG_TESTS=1): the single-turbine
 case over 2000 steps (about seven rotor revolutions), thrust, torque and
-power time series against the FP64 oracle. About four minutes of oracle time
-on 16 host cores."""
+power time series against the FP64 oracle (about four minutes of oracle
+time on 16 host cores), and the 512^3 headline box over 200 steps with FP32,
+FP16 and BF16 storage (about fourteen minutes)."""
 import os
 
 import numpy as np
@@ -12,7 +13,7 @@ import workloads
 
 pytestmark = [pytest.mark.gpu,
               pytest.mark.skipif(not os.environ.get("LBM_LONG_TESTS"),
-                                 reason="long run (~4 min of FP64 oracle time); set LBM_LONG_TESTS=1")]
+                                 reason="long runs (4 and 14 min of FP64 oracle time); set LBM_LONG_TESTS=1")]
 
 
 def test_single_turbine_loads_over_2000_steps():
@@ -49,3 +50,40 @@ def test_single_turbine_loads_over_2000_steps():
           f"last-step thrust {lg[-1, 0]:.5f} (oracle {lr[-1, 0]:.5f}), power {lg[-1, 2]:.6f} "
           f"(oracle {lr[-1, 2]:.6f})")
     assert err <= 1e-3
+
+
+def test_storage_errors_512_full_box_200_steps():
+    """The headline workload itself: the 512^3 random-phase box, 200 steps,
+    FP32 / FP16 / BF16 storage against the FP64 oracle on the whole box and
+    on the 128^3 crop at the origin (the FP16 gate is 1e-3). About 12 minutes
+    of oracle time on 16 host cores and 60 GB of host memory."""
+    import time
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2402_13171_amd.lbm import Lbm
+    n, steps = 512, 200
+    rho, u = workloads.random_phase_field(n, seed=0)
+    ref = oracle.Grid(n, n, n, omega=1.9)
+    ref.init_fields(rho, u)
+    t0 = time.time()
+    for k in range(0, steps, 20):
+        ref.step(20)
+        print(f"oracle 512^3: step {k + 20}, {time.time() - t0:.0f} s", flush=True)
+    _, u_ref = ref.fields()
+    del ref
+    den = np.linalg.norm(u_ref, axis=0)
+    dmax, cmax = den.max(), den[:128, :128, :128].max()
+    for storage, tol in (("f32", 1e-5), ("f16", 1e-3), ("bf16", None)):
+        sim = Lbm(n, n, n, omega=1.9, storage=storage)
+        sim.init_fields(rho, u)
+        sim.step(steps)
+        _, ug = sim.fields()
+        sim.close()
+        d = np.linalg.norm(ug - u_ref, axis=0)
+        err, crop = d.max() / dmax, d[:128, :128, :128].max() / cmax
+        l2 = np.sqrt((d ** 2).sum() / (den ** 2).sum())
+        print(f"512^3, {steps} steps, {storage}: eps_max {err:.3e} (crop {crop:.3e}), L2 rel {l2:.3e}", flush=True)
+        del ug, d
+        if tol is not None:
+            assert err <= tol
