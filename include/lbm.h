@@ -248,6 +248,12 @@ int lbm_set_turbine(lbm_ctx *ctx, int turbine_id, const lbm_turbine *turbine);
  * (pts[n_points_total][9]: position x[3], velocity v[3], force F[3]; points
  * in node order, rings before azimuth on disks). Synchronises. */
 int lbm_turbine_loads(lbm_ctx *ctx, int turbine_id, double *node_loads, double *pts);
+/* Spreading box of a turbine: the inclusive lattice-node range lo..hi per
+ * axis that holds the spreading support of every point at every time (the
+ * box lbm_set_turbine allocates and requires inside the domain). Checks the
+ * turbine like lbm_set_turbine; needs no context and no device. */
+int lbm_turbine_box(const lbm_turbine *turbine, int lo[3], int hi[3]);
+
 /* Number of points of the turbine in slot turbine_id (size of pts above). */
 int lbm_turbine_points(const lbm_ctx *ctx, int turbine_id, int *n_points_total);
 

@@ -599,9 +599,23 @@ bool all_finite(const double *a, int n) {
 
 }  // namespace
 
-int lbm_set_turbine(lbm_ctx *c, int id, const lbm_turbine *tb) {
-    if (!c) return LBM_EINVAL;
-    if (id < 0 || id >= MAX_ROTORS || !tb || !tb->nodes) return fail(c, LBM_EINVAL, "bad turbine id or null turbine");
+namespace {
+
+// A validated turbine: its points in node order (disks: rings before
+// azimuth), the node of each point, the polar grid and the spreading box
+// (inclusive node range, not yet checked against a domain).
+struct TurbineBuild {
+    std::vector<TreePointDev> pts;
+    std::vector<int> pt_node;
+    bool any_blade = false;
+    double a0 = 0.0, da = 1.0;
+    int b0[3], b1[3];
+};
+
+// Argument checks, points and spreading box of a turbine; c may be null
+// (then errors carry no message).
+int build_turbine(lbm_ctx *c, const lbm_turbine *tb, TurbineBuild &out) {
+    if (!tb || !tb->nodes) return fail(c, LBM_EINVAL, "null turbine");
     if (tb->n_nodes < 1 || tb->n_nodes > TREE_MAX_NODES)
         return fail(c, LBM_EINVAL, "n_nodes must be in [1, %d]", TREE_MAX_NODES);
     if (tb->kernel != LBM_KERNEL_GAUSS && tb->kernel != LBM_KERNEL_ROMA3)
@@ -609,7 +623,6 @@ int lbm_set_turbine(lbm_ctx *c, int id, const lbm_turbine *tb) {
     if (tb->kernel == LBM_KERNEL_GAUSS && !(tb->eps > 0.0 && std::isfinite(tb->eps)))
         return fail(c, LBM_EINVAL, "eps must be positive");
     if (!std::isfinite(tb->radius)) return fail(c, LBM_EINVAL, "non-finite radius");
-    bool any_blade = false;
     int npts = 0;
     for (int k = 0; k < tb->n_nodes; ++k) {
         const lbm_node &N = tb->nodes[k];
@@ -660,7 +673,7 @@ int lbm_set_turbine(lbm_ctx *c, int id, const lbm_turbine *tb) {
             for (int m = 0; m < N.n_points; ++m)
                 if (!(std::fabs(N.twist[m] + N.pitch_deg) < 180.0))
                     return fail(c, LBM_EINVAL, "node %d: |twist + pitch| must stay below 180 degrees", k);
-            any_blade = true;
+            out.any_blade = true;
         }
         if (N.force == LBM_FORCE_DRAG && N.kind == LBM_NODE_LINE && !N.chord)
             return fail(c, LBM_EINVAL, "node %d: line drag needs the diameters (chord)", k);
@@ -669,21 +682,20 @@ int lbm_set_turbine(lbm_ctx *c, int id, const lbm_turbine *tb) {
         npts += (int)np;
     }
     if (npts < 1) return fail(c, LBM_EINVAL, "a turbine needs at least one point");
-    double a0 = 0.0, da = 1.0;
-    if (any_blade) {
+    if (out.any_blade) {
         if (tb->n_polar < 2 || !tb->alpha_deg || !tb->cl || !tb->cd) return fail(c, LBM_EINVAL, "missing polars");
         if (!all_finite(tb->alpha_deg, tb->n_polar) || !all_finite(tb->cl, tb->n_polar) || !all_finite(tb->cd, tb->n_polar))
             return fail(c, LBM_EINVAL, "non-finite polar value");
-        a0 = tb->alpha_deg[0];
-        da = (tb->alpha_deg[tb->n_polar - 1] - a0) / (tb->n_polar - 1);
-        if (!(da > 0.0)) return fail(c, LBM_EINVAL, "polar angles must ascend");
+        out.a0 = tb->alpha_deg[0];
+        out.da = (tb->alpha_deg[tb->n_polar - 1] - out.a0) / (tb->n_polar - 1);
+        if (!(out.da > 0.0)) return fail(c, LBM_EINVAL, "polar angles must ascend");
         for (int k = 0; k < tb->n_polar; ++k)
-            if (std::fabs(tb->alpha_deg[k] - (a0 + k * da)) > 1e-9 * (1.0 + std::fabs(a0)))
+            if (std::fabs(tb->alpha_deg[k] - (out.a0 + k * out.da)) > 1e-9 * (1.0 + std::fabs(out.a0)))
                 return fail(c, LBM_EINVAL, "polar angle grid must be uniform");
     }
     // points in node order (disks: rings before azimuth), element data
-    std::vector<TreePointDev> pts;
-    std::vector<int> pt_node;
+    std::vector<TreePointDev> &pts = out.pts;
+    std::vector<int> &pt_node = out.pt_node;
     for (int k = 0; k < tb->n_nodes; ++k) {
         const lbm_node &N = tb->nodes[k];
         if (N.kind == LBM_NODE_LINE) {
@@ -717,7 +729,11 @@ int lbm_set_turbine(lbm_ctx *c, int id, const lbm_turbine *tb) {
     const int half = tb->kernel == LBM_KERNEL_ROMA3 ? 1 : SUPPORT;
     std::vector<HostPose> ref;
     reference_poses(tb, ref);
-    int b0[3] = {1 << 30, 1 << 30, 1 << 30}, b1[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
+    int *b0 = out.b0, *b1 = out.b1;
+    for (int a = 0; a < 3; ++a) {
+        b0[a] = 1 << 30;
+        b1[a] = -(1 << 30);
+    }
     for (const TreePointDev &p : pts) {
         double lo[3], hi[3];
         point_reach(tb, ref, p.node, p.q, lo, hi);
@@ -727,6 +743,25 @@ int lbm_set_turbine(lbm_ctx *c, int id, const lbm_turbine *tb) {
             b1[a] = std::max(b1[a], (int)std::floor(hi[a] + 0.5 + 1e-9) + half);
         }
     }
+    return LBM_OK;
+}
+
+}  // namespace
+
+int lbm_set_turbine(lbm_ctx *c, int id, const lbm_turbine *tb) {
+    if (!c) return LBM_EINVAL;
+    if (id < 0 || id >= MAX_ROTORS || !tb || !tb->nodes) return fail(c, LBM_EINVAL, "bad turbine id or null turbine");
+    TurbineBuild tbd;
+    {
+        const int rc = build_turbine(c, tb, tbd);
+        if (rc != LBM_OK) return rc;
+    }
+    const std::vector<TreePointDev> &pts = tbd.pts;
+    const bool any_blade = tbd.any_blade;
+    const double a0 = tbd.a0, da = tbd.da;
+    const int npts = (int)pts.size();
+    const int half = tb->kernel == LBM_KERNEL_ROMA3 ? 1 : SUPPORT;
+    const int *b0 = tbd.b0, *b1 = tbd.b1;
     const int dims[3] = {c->cfg.nx, c->cfg.ny, c->cfg.nz};
     for (int a = 0; a < 3; ++a)
         if (b0[a] < 0 || b1[a] >= dims[a])
@@ -817,7 +852,7 @@ int lbm_set_turbine(lbm_ctx *c, int id, const lbm_turbine *tb) {
         D.Fbox = R.d_Fbox;
         R.npts = npts;
         R.n_nodes = tb->n_nodes;
-        R.pt_node = pt_node;
+        R.pt_node = tbd.pt_node;
         R.on = true;
         return LBM_OK;
     }();
@@ -827,6 +862,18 @@ int lbm_set_turbine(lbm_ctx *c, int id, const lbm_turbine *tb) {
         return rc;
     }
     return refresh_rotor_table(c);
+}
+
+int lbm_turbine_box(const lbm_turbine *tb, int lo[3], int hi[3]) {
+    if (!lo || !hi) return LBM_EINVAL;
+    TurbineBuild tbd;
+    const int rc = build_turbine(nullptr, tb, tbd);
+    if (rc != LBM_OK) return rc;
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = tbd.b0[a];
+        hi[a] = tbd.b1[a];
+    }
+    return LBM_OK;
 }
 
 int lbm_turbine_points(const lbm_ctx *c, int id, int *n_points_total) {

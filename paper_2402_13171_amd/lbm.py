@@ -28,7 +28,7 @@ EXPORTS = [
     "lbm_strerror", "lbm_last_error", "lbm_copy_probe", "lbm_pattern_probe",
     "lbm_mlp_create", "lbm_mlp_destroy", "lbm_mlp_set_params", "lbm_mlp_get_params",
     "lbm_mlp_forward", "lbm_mlp_loss_grad", "lbm_mlp_adam_step", "lbm_mlp_take_loss",
-    "lbm_mlp_last_error", "lbm_set_turbine", "lbm_turbine_loads", "lbm_turbine_points",
+    "lbm_mlp_last_error", "lbm_set_turbine", "lbm_turbine_loads", "lbm_turbine_points", "lbm_turbine_box",
 ]
 
 
@@ -109,6 +109,7 @@ def lib():
         "lbm_set_turbine": [vp, i, C.POINTER(Turbine)],
         "lbm_turbine_loads": [vp, i, _D, _D],
         "lbm_turbine_points": [vp, i, C.POINTER(i)],
+        "lbm_turbine_box": [C.POINTER(Turbine), C.POINTER(i), C.POINTER(i)],
         "lbm_step": [vp, i],
         "lbm_set_inflow": [vp, _D, _D, i, C.c_double],
         "lbm_get_fields": [vp, _D, _D],
@@ -163,6 +164,62 @@ def _f64(a):
 
 def _p(a):
     return a.ctypes.data_as(_D)
+
+
+def _turbine_struct(turbine):
+    """ctypes lbm_turbine of a workloads.turbines dict, and the arrays it
+    points into (keep them alive while the struct is used)."""
+    nodes = turbine["nodes"]
+    arr = (Node * len(nodes))()
+    keep = [arr]
+    for k, nd in enumerate(nodes):
+        d = arr[k]
+        d.parent = nd.get("parent", -1)
+        d.kind = NODE_KINDS[nd.get("kind", "frame")]
+        d.force = FORCE_MODELS[nd.get("force", "none")]
+        d.n_azimuth = nd.get("n_azimuth", 0)
+        d.tip_loss = int(bool(nd.get("tip_loss", False)))
+        rot = np.asarray(nd.get("rot", np.eye(3)), dtype=np.float64).reshape(9)
+        for a in range(9):
+            d.rot[a] = rot[a]
+        for name in ("pos", "axis", "disp", "dir", "normal"):
+            vec = nd.get(name, (1.0, 0.0, 0.0) if name == "axis" else (0.0, 0.0, 0.0))
+            for a in range(3):
+                getattr(d, name)[a] = vec[a]
+        for name in ("omega", "angle0", "amp", "freq", "phase", "coef", "pitch_deg"):
+            setattr(d, name, float(nd.get(name, 0.0)))
+        n = 0
+        for name in ("s", "width", "chord", "twist"):
+            if nd.get(name) is not None:
+                a = _f64(nd[name])
+                keep.append(a)
+                setattr(d, name, _p(a))
+                n = len(a)
+        d.n_points = n
+    t = Turbine()
+    t.n_nodes, t.nodes = len(nodes), arr
+    t.kernel = KERNELS[turbine.get("kernel", "gauss")]
+    t.eps = float(turbine.get("eps", 2.0))
+    t.n_blades = int(turbine.get("n_blades", 0))
+    t.radius = float(turbine.get("radius", 0.0))
+    pol = turbine.get("polar")
+    if pol is not None:
+        pa = {k: _f64(pol[k]) for k in ("alpha_deg", "cl", "cd")}
+        keep += list(pa.values())
+        t.n_polar = len(pa["alpha_deg"])
+        t.alpha_deg, t.cl, t.cd = _p(pa["alpha_deg"]), _p(pa["cl"]), _p(pa["cd"])
+    return t, keep
+
+
+def turbine_box(turbine):
+    """Inclusive lattice-node ranges (lo[3], hi[3]) of the turbine's spreading
+    box (lbm_turbine_box; no device needed)."""
+    t, keep = _turbine_struct(turbine)
+    lo, hi = (C.c_int * 3)(), (C.c_int * 3)()
+    rc = lib().lbm_turbine_box(C.byref(t), lo, hi)
+    if rc != OK:
+        raise LbmError(rc, lib().lbm_strerror(rc).decode())
+    return list(lo), list(hi)
 
 
 class Lbm:
@@ -309,45 +366,8 @@ class Lbm:
     def set_turbine(self, tid, turbine):
         """turbine: dict of workloads.turbines (nodes with parent, kind,
         force, pose, motion and per-point arrays; kernel, eps, polars)."""
+        t, keep = _turbine_struct(turbine)
         nodes = turbine["nodes"]
-        arr = (Node * len(nodes))()
-        keep = [arr]
-        for k, nd in enumerate(nodes):
-            d = arr[k]
-            d.parent = nd.get("parent", -1)
-            d.kind = NODE_KINDS[nd.get("kind", "frame")]
-            d.force = FORCE_MODELS[nd.get("force", "none")]
-            d.n_azimuth = nd.get("n_azimuth", 0)
-            d.tip_loss = int(bool(nd.get("tip_loss", False)))
-            rot = np.asarray(nd.get("rot", np.eye(3)), dtype=np.float64).reshape(9)
-            for a in range(9):
-                d.rot[a] = rot[a]
-            for name in ("pos", "axis", "disp", "dir", "normal"):
-                vec = nd.get(name, (1.0, 0.0, 0.0) if name == "axis" else (0.0, 0.0, 0.0))
-                for a in range(3):
-                    getattr(d, name)[a] = vec[a]
-            for name in ("omega", "angle0", "amp", "freq", "phase", "coef", "pitch_deg"):
-                setattr(d, name, float(nd.get(name, 0.0)))
-            n = 0
-            for name in ("s", "width", "chord", "twist"):
-                if nd.get(name) is not None:
-                    a = _f64(nd[name])
-                    keep.append(a)
-                    setattr(d, name, _p(a))
-                    n = len(a)
-            d.n_points = n
-        t = Turbine()
-        t.n_nodes, t.nodes = len(nodes), arr
-        t.kernel = KERNELS[turbine.get("kernel", "gauss")]
-        t.eps = float(turbine.get("eps", 2.0))
-        t.n_blades = int(turbine.get("n_blades", 0))
-        t.radius = float(turbine.get("radius", 0.0))
-        pol = turbine.get("polar")
-        if pol is not None:
-            pa = {k: _f64(pol[k]) for k in ("alpha_deg", "cl", "cd")}
-            keep += list(pa.values())
-            t.n_polar = len(pa["alpha_deg"])
-            t.alpha_deg, t.cl, t.cd = _p(pa["alpha_deg"]), _p(pa["cl"]), _p(pa["cd"])
         self._check(lib().lbm_set_turbine(self._ctx, tid, C.byref(t)))
         npt = C.c_int()
         self._check(lib().lbm_turbine_points(self._ctx, tid, C.byref(npt)))
