@@ -314,8 +314,12 @@ int lbm_mlp_adam_step(lbm_mlp *m, float lr, float beta1, float beta2, float eps)
 int lbm_mlp_take_loss(lbm_mlp *m, double *mean_loss);
 const char *lbm_mlp_last_error(const lbm_mlp *m);
 
-/* Checkpoint: raw population store, outflow ghost plane, time and layout
- * parity. lbm_state_bytes gives the size. Synchronises. */
+/* Checkpoint: raw population store, outflow ghost plane, time, layout
+ * parity and the force boxes of the rotor and turbine slots (the spread
+ * force of the last step, half of which the next step's sampled velocity
+ * includes). lbm_state_bytes gives the size. Restore into a context with the
+ * same configuration and the same rotors and turbines set (else
+ * LBM_EINVAL). Synchronises. */
 int lbm_state_bytes(const lbm_ctx *ctx, size_t *bytes);
 int lbm_get_state(lbm_ctx *ctx, void *host_buf, size_t bytes);
 int lbm_set_state(lbm_ctx *ctx, const void *host_buf, size_t bytes);

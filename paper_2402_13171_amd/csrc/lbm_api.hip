@@ -1183,9 +1183,20 @@ int lbm_set_closure_weights(lbm_ctx *c, const float *w, size_t n) {
     return LBM_OK;
 }
 
+// bytes of the force boxes of the active rotor / turbine slots (slot order)
+static size_t box_state_bytes(const lbm_ctx *c) {
+    size_t n = 0;
+    for (int r = 0; r < MAX_ROTORS; ++r)
+        if (c->rot[r].on) {
+            const ForceBox &B = c->rot[r].dev.box;
+            n += (size_t)3 * B.bnx * B.bny * B.bnz * sizeof(float);
+        }
+    return n;
+}
+
 int lbm_state_bytes(const lbm_ctx *c, size_t *bytes) {
     if (!c || !bytes) return LBM_EINVAL;
-    *bytes = 64 + c->pop_bytes + c->off_uin;
+    *bytes = 64 + c->pop_bytes + c->off_uin + box_state_bytes(c);
     return LBM_OK;
 }
 
@@ -1197,11 +1208,20 @@ int lbm_get_state(lbm_ctx *c, void *buf, size_t bytes) {
     if (!buf || bytes < need) return fail(c, LBM_EINVAL, "state buffer needs %zu bytes", need);
     char *b = (char *)buf;
     memset(b, 0, 64);
-    const long hdr[4] = {0x4c424d31L, c->t, c->parity, (long)c->cfg.storage};
+    const long hdr[5] = {0x4c424d31L, c->t, c->parity, (long)c->cfg.storage, (long)box_state_bytes(c)};
     memcpy(b, hdr, sizeof hdr);
     HIPCHK(c, hipMemcpyAsync(b + 64, c->pops, c->pop_bytes, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipMemcpyAsync(b + 64 + c->pop_bytes, (char *)c->aux + c->off_ghost, c->off_uin, hipMemcpyDeviceToHost,
                              c->stream));
+    // the spread force of the last step: the next step samples u with half of it
+    size_t off = 64 + c->pop_bytes + c->off_uin;
+    for (int r = 0; r < MAX_ROTORS; ++r)
+        if (c->rot[r].on) {
+            const ForceBox &B = c->rot[r].dev.box;
+            const size_t nbytes = (size_t)3 * B.bnx * B.bny * B.bnz * sizeof(float);
+            HIPCHK(c, hipMemcpyAsync(b + off, c->rot[r].d_Fbox, nbytes, hipMemcpyDeviceToHost, c->stream));
+            off += nbytes;
+        }
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return LBM_OK;
 }
@@ -1213,13 +1233,24 @@ int lbm_set_state(lbm_ctx *c, const void *buf, size_t bytes) {
     lbm_state_bytes(c, &need);
     if (!buf || bytes < need) return fail(c, LBM_EINVAL, "state buffer needs %zu bytes", need);
     const char *b = (const char *)buf;
-    long hdr[4];
+    long hdr[5];
     memcpy(hdr, b, sizeof hdr);
     if (hdr[0] != 0x4c424d31L || hdr[3] != (long)c->cfg.storage || (hdr[2] != 0 && hdr[2] != 1))
         return fail(c, LBM_EINVAL, "state header does not match this context");
+    if (hdr[4] != (long)box_state_bytes(c))
+        return fail(c, LBM_EINVAL, "state holds %ld bytes of rotor force boxes, this context's slots %zu: set the "
+                                   "same rotors and turbines before restoring", hdr[4], box_state_bytes(c));
     HIPCHK(c, hipMemcpyAsync(c->pops, b + 64, c->pop_bytes, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync((char *)c->aux + c->off_ghost, b + 64 + c->pop_bytes, c->off_uin, hipMemcpyHostToDevice,
                              c->stream));
+    size_t off = 64 + c->pop_bytes + c->off_uin;
+    for (int r = 0; r < MAX_ROTORS; ++r)
+        if (c->rot[r].on) {
+            const ForceBox &B = c->rot[r].dev.box;
+            const size_t nbytes = (size_t)3 * B.bnx * B.bny * B.bnz * sizeof(float);
+            HIPCHK(c, hipMemcpyAsync(c->rot[r].d_Fbox, b + off, nbytes, hipMemcpyHostToDevice, c->stream));
+            off += nbytes;
+        }
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->t = hdr[1];
     c->parity = (int)hdr[2];

@@ -270,3 +270,42 @@ def test_rotors_and_a_turbine_in_one_box():
     e = check_fields(sim, ref, 1e-5)
     print(f"two rotors + a disk: worst load error {worst:.2e}, field {e:.2e}")
     assert worst <= 2e-5
+
+
+def test_checkpoint_resume_with_rotor_and_turbine_is_bitwise():
+    """A run resumed from a checkpoint repeats the uninterrupted run bit for
+    bit, rotor and turbine loads included: the state carries the slots'
+    spread force of the last step, which the next step's sampling uses. A
+    context without the same slots refuses the state."""
+    _need_gpu()
+    from paper_2402_13171_amd.lbm import Lbm, LbmError
+    shape = (64, 48, 48)
+    ra = _rotor((14.0, 23.5, 24.0), R=6.0)
+    tr = TB.hawt(_rotor((40.0, 23.5, 28.0), R=6.0), base_z=8.0, overhang=2.0, tower_spacing=4.0)
+    sim = Lbm(*shape, omega=1.8, bc_x="inout", bc_z=("noslip", "freeslip"), u_in=(0.05, 0.0, 0.0))
+    rho, u = _uniform(shape)
+    sim.init_fields(rho, u)
+    sim.set_rotor(0, ra)
+    sim.set_turbine(1, tr)
+    sim.step(5)
+    state = sim.get_state()
+
+    def run(k):
+        out = []
+        for _ in range(k):
+            sim.step(1)
+            out.append((sim.rotor_loads(0).copy(), sim.turbine_loads(1)[0].copy()))
+        return out, sim.pops()
+
+    a, pa = run(3)
+    sim.set_state(state)
+    assert sim.time == 5
+    b, pb = run(3)
+    assert np.array_equal(pa, pb)
+    for (ra_, ta), (rb_, tb_) in zip(a, b):
+        assert np.array_equal(ra_, rb_) and np.array_equal(ta, tb_)
+    other = Lbm(*shape, omega=1.8, bc_x="inout", bc_z=("noslip", "freeslip"), u_in=(0.05, 0.0, 0.0))
+    other.init_fields(rho, u)
+    other.set_rotor(0, ra)
+    with pytest.raises(LbmError):
+        other.set_state(state)  # the turbine slot is missing
