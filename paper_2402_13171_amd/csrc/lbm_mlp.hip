@@ -201,19 +201,37 @@ __global__ __launch_bounds__(GW) void k_mlp_grad(const MlpDev *M, const float *f
     if (lane == 0) loss_partials[blockIdx.x] = l;
 }
 
-// fixed-order sum of the per-wave partials
-__global__ __launch_bounds__(TB) void k_mlp_reduce(const float *partials, int nwaves, float *grad,
-                                                   const double *loss_partials, double count, double *loss_acc) {
+// Fixed-order sum of the per-wave partials in two stages: group g (blockIdx.y)
+// adds waves [g per, (g+1) per) in FP64 for every parameter and the loss
+// (index MLP_NPARAM), then one pass adds the groups in order. The grouping
+// depends only on the batch size, so the result is deterministic.
+constexpr int RED_GROUPS = 64;
+__global__ __launch_bounds__(TB) void k_mlp_reduce_groups(const float *partials, const double *loss_partials,
+                                                          int nwaves, int per, double *groups) {
+    const int prm = blockIdx.x * TB + threadIdx.x, g = blockIdx.y;
+    if (prm > MLP_NPARAM) return;
+    const int w0 = g * per, w1 = min(nwaves, w0 + per);
+    double a = 0.0;
+    if (prm < MLP_NPARAM)
+#pragma unroll 8
+        for (int w = w0; w < w1; ++w) a += partials[(size_t)w * MLP_NPARAM + prm];
+    else
+        for (int w = w0; w < w1; ++w) a += loss_partials[w];
+    groups[(size_t)g * (MLP_NPARAM + 1) + prm] = a;
+}
+
+__global__ __launch_bounds__(TB) void k_mlp_reduce(const double *groups, int ngroups, float *grad, double count,
+                                                   double *loss_acc) {
     const int prm = blockIdx.x * TB + threadIdx.x;
+    if (prm > MLP_NPARAM) return;
+    double a = 0.0;
+    // unrolled so that the loads are issued ahead; the additions keep their order
+#pragma unroll 8
+    for (int g = 0; g < ngroups; ++g) a += groups[(size_t)g * (MLP_NPARAM + 1) + prm];
     if (prm < MLP_NPARAM) {
-        double a = 0.0;
-        for (int w = 0; w < nwaves; ++w) a += partials[(size_t)w * MLP_NPARAM + prm];
         grad[prm] = (float)a;
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        double l = 0.0;
-        for (int w = 0; w < nwaves; ++w) l += loss_partials[w];
-        loss_acc[0] += l;
+    } else {
+        loss_acc[0] += a;
         loss_acc[1] += count;
     }
 }
@@ -264,7 +282,7 @@ struct lbm_mlp {
     bool own_stream = false;
     MlpDev *d_M = nullptr;
     float *d_params = nullptr, *d_m = nullptr, *d_v = nullptr, *d_grad = nullptr, *d_part = nullptr;
-    double *d_lpart = nullptr, *d_loss = nullptr;
+    double *d_lpart = nullptr, *d_loss = nullptr, *d_groups = nullptr;
     size_t cap_waves = 0;
     float blob_tail[13] = {0};
     int step = 0;
@@ -319,7 +337,8 @@ int lbm_mlp_create(void *stream, lbm_mlp **out) {
               hipMalloc((void **)&m->d_m, MLP_NPARAM * sizeof(float)) == hipSuccess &&
               hipMalloc((void **)&m->d_v, MLP_NPARAM * sizeof(float)) == hipSuccess &&
               hipMalloc((void **)&m->d_grad, MLP_NPARAM * sizeof(float)) == hipSuccess &&
-              hipMalloc((void **)&m->d_loss, 2 * sizeof(double)) == hipSuccess;
+              hipMalloc((void **)&m->d_loss, 2 * sizeof(double)) == hipSuccess &&
+              hipMalloc((void **)&m->d_groups, (size_t)RED_GROUPS * (MLP_NPARAM + 1) * sizeof(double)) == hipSuccess;
     if (!ok || hipMemsetAsync(m->d_loss, 0, 2 * sizeof(double), m->stream) != hipSuccess) {
         lbm_mlp_destroy(m);
         return LBM_ENOMEM;
@@ -331,7 +350,7 @@ int lbm_mlp_create(void *stream, lbm_mlp **out) {
 int lbm_mlp_destroy(lbm_mlp *m) {
     if (!m) return LBM_EINVAL;
     if (m->stream) (void)hipStreamSynchronize(m->stream);
-    void *ptrs[] = {m->d_M, m->d_params, m->d_m, m->d_v, m->d_grad, m->d_part, m->d_lpart, m->d_loss};
+    void *ptrs[] = {m->d_M, m->d_params, m->d_m, m->d_v, m->d_grad, m->d_part, m->d_lpart, m->d_loss, m->d_groups};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (m->own_stream) (void)hipStreamDestroy(m->stream);
@@ -387,8 +406,11 @@ int lbm_mlp_loss_grad(lbm_mlp *m, const float *d_feat, const float *d_target, si
     if (rc) return rc;
     k_mlp_grad<<<(unsigned)nw, GW, 0, m->stream>>>(m->d_M, d_feat, d_target, count, 1.0f / (float)count, m->d_part,
                                                    m->d_lpart);
-    k_mlp_reduce<<<(MLP_NPARAM + TB - 1) / TB, TB, 0, m->stream>>>(m->d_part, (int)nw, m->d_grad, m->d_lpart,
-                                                                  (double)count, m->d_loss);
+    const int per = (int)((nw + RED_GROUPS - 1) / RED_GROUPS), ngroups = (int)((nw + per - 1) / per);
+    const unsigned pblocks = (MLP_NPARAM + 1 + TB - 1) / TB;
+    k_mlp_reduce_groups<<<dim3(pblocks, ngroups), TB, 0, m->stream>>>(m->d_part, m->d_lpart, (int)nw, per,
+                                                                      m->d_groups);
+    k_mlp_reduce<<<pblocks, TB, 0, m->stream>>>(m->d_groups, ngroups, m->d_grad, (double)count, m->d_loss);
     MCHK(m, hipGetLastError());
     m->has_grad = true;
     if (grad) {
