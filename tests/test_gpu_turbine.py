@@ -309,3 +309,34 @@ def test_checkpoint_resume_with_rotor_and_turbine_is_bitwise():
     other.set_rotor(0, ra)
     with pytest.raises(LbmError):
         other.set_state(state)  # the turbine slot is missing
+
+
+def test_hawt_tree_in_the_single_turbine_box_200_steps():
+    """The run_turbine tree case at full size (256 x 128 x 128, inflow /
+    outflow, the D = 32 rotor with tower and nacelle face, 140 points) for 200
+    steps: node loads within 1e-3 of the largest load of each kind every
+    10 steps, and the flow within 1e-4 at the end."""
+    _need_gpu()
+    from paper_2402_13171_amd.lbm import Lbm
+    shape = (256, 128, 128)
+    tr = TB.hawt(workloads.single_turbine_rotor(), base_z=8.0, overhang=3.0)
+    print("HAWT tree, 256x128x128, 200 steps (FP64 oracle on the host: ~30 s)", flush=True)
+    sim = Lbm(*shape, omega=1.9, bc_x="inout", u_in=(0.05, 0.0, 0.0))
+    ref = oracle.Grid(*shape, omega=1.9, bc_x=oracle.INOUT, u_in=(0.05, 0.0, 0.0))
+    rho, u = _uniform(shape)
+    sim.init_fields(rho, u)
+    ref.init_fields(rho, u)
+    sim.set_turbine(0, tr)
+    ref.set_turbine(0, tr)
+    worst = 0.0
+    for s in range(20):
+        sim.step(10)
+        ref.step(10)
+        nlg, _ = sim.turbine_loads(0)
+        nlr, _ = ref.turbine_loads(0)
+        for cols in (slice(0, 3), slice(3, 6), slice(6, 7)):
+            sc = np.abs(nlr[:, cols]).max()
+            worst = max(worst, np.abs(nlg[:, cols] - nlr[:, cols]).max() / sc)
+    e = check_fields(sim, ref, 1e-4)
+    print(f"HAWT tree 200 steps: worst node-load error {worst:.2e}, field {e:.2e}")
+    assert worst <= 1e-3
