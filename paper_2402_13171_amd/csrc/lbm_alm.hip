@@ -72,6 +72,8 @@ __device__ __forceinline__ void cross3(const double *a, const double *b, double 
 }
 __device__ __forceinline__ double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
 
+static_assert(sizeof(NodeDev) % 8 == 0 && alignof(NodeDev) == 8, "node table copied as 8-byte words");
+
 __device__ void tree_pose(const NodeDev *nodes, int node, double t, TreePose &P) {
     int chain[TREE_MAX_DEPTH];
     int d = 0;
@@ -186,8 +188,17 @@ __global__ __launch_bounds__(ALM_BLOCK) void k_alm_points(Geo g, Physics ph, Rot
     __shared__ double s_corner[ALM_BLOCK][4];  // rho, u of one corner cell per work item
     __shared__ double s_red[ALM_BATCH][2];
     __shared__ TreePose s_pose[TREE_MAX_NODES];  // turbine: every node's pose at this step
+    __shared__ NodeDev s_nodes[TREE_MAX_NODES];  // turbine: the node table
     if (R.nodes) {
-        if (threadIdx.x < R.n_nodes) tree_pose(R.nodes, threadIdx.x, (double)t, s_pose[threadIdx.x]);
+        // one coalesced copy of the node table, so that the pose recursion
+        // walks the parent chain in LDS rather than through one dependent
+        // global load per level (n_nodes <= TREE_MAX_NODES, checked on the host)
+        constexpr int NW = (int)(sizeof(NodeDev) / 8);
+        const unsigned long long *src = (const unsigned long long *)R.nodes;
+        unsigned long long *dst = (unsigned long long *)s_nodes;
+        for (int q = threadIdx.x; q < R.n_nodes * NW; q += ALM_BLOCK) dst[q] = src[q];
+        __syncthreads();
+        if (threadIdx.x < R.n_nodes) tree_pose(s_nodes, threadIdx.x, (double)t, s_pose[threadIdx.x]);
         __syncthreads();
     }
     {
@@ -243,7 +254,7 @@ __global__ __launch_bounds__(ALM_BLOCK) void k_alm_points(Geo g, Physics ph, Rot
                 accQ = rr * Ft;
             } else {
                 const TreePointDev &tp = R.tpts[p];
-                const NodeDev &N = R.nodes[tp.node];
+                const NodeDev &N = s_nodes[tp.node];
                 const double W[3] = {sm[1] - vp[0], sm[2] - vp[1], sm[3] - vp[2]};
                 if (N.force == LBM_FORCE_BLADE) {
                     double es[3], en[3], et[3];
