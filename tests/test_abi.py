@@ -62,3 +62,15 @@ def test_error_strings_without_gpu():
     cfg.omega = 1.9
     cfg.bc_z_lo = 2  # one periodic and one wall side is not allowed
     assert L.lbm_create(ctypes.byref(cfg), ctypes.byref(h)) == lbm.EINVAL
+
+
+def test_copy_probe_validates_before_any_device_work():
+    from paper_2402_13171_amd import lbm
+    L = lbm.lib()
+    vp = ctypes.c_void_p
+    assert L.lbm_copy_probe(None, vp(256), 4096, None) == lbm.EINVAL
+    assert L.lbm_copy_probe(vp(256), None, 4096, None) == lbm.EINVAL
+    assert L.lbm_copy_probe(vp(256), vp(512), 4100, None) == lbm.EINVAL   # not a multiple of 16 bytes
+    assert L.lbm_copy_probe(vp(264), vp(512), 4096, None) == lbm.EINVAL   # source not 16-byte aligned
+    assert L.lbm_copy_probe(vp(256), vp(520), 4096, None) == lbm.EINVAL   # destination not 16-byte aligned
+    assert L.lbm_copy_probe(vp(256), vp(512), 0, None) == lbm.OK          # nothing to copy: no launch
