@@ -325,10 +325,13 @@ int lbm_get_state(lbm_ctx *ctx, void *host_buf, size_t bytes);
 int lbm_set_state(lbm_ctx *ctx, const void *host_buf, size_t bytes);
 
 /* Device-to-device copy of `bytes` (multiple of 16, 16-byte aligned device
- * pointers) with a plain streaming kernel, enqueued on `stream` (hipStream_t
- * or NULL). It measures achievable HBM bandwidth, the reference the paper
- * takes from the STREAM copy kernel (Sec. 4.3), and calibrates hardware
- * traffic counters against a kernel of known traffic. */
+ * pointers) with a plain streaming kernel (one 16-byte element per thread,
+ * 256-thread groups), enqueued on `stream` (hipStream_t or NULL). It measures
+ * achievable HBM bandwidth, the reference the paper takes from the STREAM
+ * copy kernel (Sec. 4.3), and calibrates hardware traffic counters against a
+ * kernel of known traffic. Null pointers, a size that is not a multiple of 16
+ * or unaligned pointers give LBM_EINVAL before any device work; bytes = 0
+ * launches nothing. The regions must not overlap. */
 int lbm_copy_probe(const void *d_src, void *d_dst, size_t bytes, void *stream);
 
 /* Access-pattern probe (measurement, Sec. 4.3's roofline): enqueue on the
