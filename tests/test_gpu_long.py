@@ -1,8 +1,10 @@
 """Long GPU <-> oracle runs, opt-in (set LBM_LONG_TESTS=1): the single-turbine
 case over 2000 steps (about seven rotor revolutions), thrust, torque and
 power time series against the FP64 oracle (about four minutes of oracle
-time on 16 host cores), and the 512^3 headline box over 200 steps with FP32,
-FP16 and BF16 storage (about fourteen minutes)."""
+time on 16 host cores); a floating turbine tree (tower, nacelle, rotor on a
+pitching and surging platform) over 2000 steps, five platform periods (about
+five minutes); and the 512^3 headline box over 200 steps with FP32, FP16 and
+BF16 storage (about fourteen minutes)."""
 import os
 
 import numpy as np
@@ -10,10 +12,11 @@ import pytest
 
 import oracle
 import workloads
+from workloads import turbines as TB
 
 pytestmark = [pytest.mark.gpu,
               pytest.mark.skipif(not os.environ.get("LBM_LONG_TESTS"),
-                                 reason="long runs (4 and 14 min of FP64 oracle time); set LBM_LONG_TESTS=1")]
+                                 reason="long runs (4, 5 and 14 min of FP64 oracle time); set LBM_LONG_TESTS=1")]
 
 
 def test_single_turbine_loads_over_2000_steps():
@@ -50,6 +53,46 @@ def test_single_turbine_loads_over_2000_steps():
           f"last-step thrust {lg[-1, 0]:.5f} (oracle {lr[-1, 0]:.5f}), power {lg[-1, 2]:.6f} "
           f"(oracle {lr[-1, 2]:.6f})")
     assert err <= 1e-3
+
+
+def test_floating_turbine_tree_over_2000_steps():
+    """Sec. 3.3 tree on a moving platform: the floating configuration of the
+    turbine-tree runs (pitch 0.05 rad and surge 1 cell at a 400-step wave
+    period, rotor turning at tip-speed ratio 7) in the 256 x 128 x 128
+    inflow box. Every node's force, moment and power within 1e-3 of the
+    largest of its kind every 10 steps over five platform periods."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2402_13171_amd.lbm import Lbm
+    nx, ny, nz = 256, 128, 128
+    tr = TB.hawt(workloads.single_turbine_rotor(), base_z=8.0, overhang=3.0, pitch_amp=0.05, surge_amp=1.0,
+                 wave_freq=2.0 * np.pi / 400.0)
+    sim = Lbm(nx, ny, nz, omega=1.9, bc_x="inout", u_in=(0.05, 0, 0))
+    ref = oracle.Grid(nx, ny, nz, omega=1.9, bc_x=oracle.INOUT, u_in=(0.05, 0, 0))
+    u = np.zeros((3, nz, ny, nx))
+    u[0] = 0.05
+    rho = np.ones((nz, ny, nx))
+    sim.init_fields(rho, u)
+    ref.init_fields(rho, u)
+    sim.set_turbine(0, tr)
+    ref.set_turbine(0, tr)
+    worst = 0.0
+    for s in range(200):
+        sim.step(10)
+        ref.step(10)
+        nlg, _ = sim.turbine_loads(0)
+        nlr, _ = ref.turbine_loads(0)
+        for cols in (slice(0, 3), slice(3, 6), slice(6, 7)):
+            sc = np.abs(nlr[:, cols]).max()
+            worst = max(worst, np.abs(nlg[:, cols] - nlr[:, cols]).max() / sc)
+        if (s + 1) % 25 == 0:
+            print(f"floating tree: step {10 * (s + 1)}, worst node-load error so far {worst:.2e}", flush=True)
+    _, ug = sim.fields()
+    _, ur = ref.fields()
+    ferr = np.linalg.norm(ug - ur, axis=0).max() / np.linalg.norm(ur, axis=0).max()
+    print(f"floating tree 2000 steps: worst node-load error {worst:.2e}, field eps_max {ferr:.2e}")
+    assert worst <= 1e-3
 
 
 def test_storage_errors_512_full_box_200_steps():
