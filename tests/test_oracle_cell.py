@@ -286,3 +286,155 @@ def test_adam_first_step_is_signed_lr():
     g = np.array([3.0, -0.5, 1e-3])
     p, m, v = mlp_ref.adam_step(np.zeros(3), g, np.zeros(3), np.zeros(3), 1, lr=0.01, eps=0.0)
     assert np.allclose(p, -0.01 * np.sign(g), rtol=1e-15)
+
+
+# ------------------------------------------------------------ relaxation groups
+# Reading of the cumulant collision (Sec. 2.1; the rates are not printed):
+# which combination of cumulants each of omega_1..omega_10 relaxes. With one
+# rate at 1/2 and every other rate at 1, every cumulant of order >= 2 goes to
+# its equilibrium except the combination that rate names, which keeps half
+# its pre-collision value. The cumulants on both sides come from the
+# set-partition definition above, applied to the populations before and
+# after the collision, not from the oracle's cumulant map.
+def _all_cumulants(f, u):
+    rho = f.sum()
+    p, X = f / rho, C27 - u
+    out = {}
+    for m in range(27):
+        a, b, c = m % 3, (m // 3) % 3, m // 9
+        if a + b + c >= 2:
+            out[(a, b, c)] = _joint_cumulant(p, X, [0] * a + [1] * b + [2] * c)
+    return out
+
+
+def _groups(C):
+    """The combinations the rates act on, as named by the reading; each is
+    a tuple of linear combinations of cumulants (equilibrium value 0 except
+    the second-order trace, whose equilibrium is 1)."""
+    g = {}
+    g[1] = (C[(1, 1, 0)], C[(1, 0, 1)], C[(0, 1, 1)],
+            C[(2, 0, 0)] - C[(0, 2, 0)], C[(2, 0, 0)] - C[(0, 0, 2)])
+    g[2] = (C[(2, 0, 0)] + C[(0, 2, 0)] + C[(0, 0, 2)] - 1.0,)
+    g[3] = (C[(1, 2, 0)] + C[(1, 0, 2)], C[(2, 1, 0)] + C[(0, 1, 2)], C[(2, 0, 1)] + C[(0, 2, 1)])
+    g[4] = (C[(1, 2, 0)] - C[(1, 0, 2)], C[(2, 1, 0)] - C[(0, 1, 2)], C[(2, 0, 1)] - C[(0, 2, 1)])
+    g[5] = (C[(1, 1, 1)],)
+    g[6] = (C[(2, 2, 0)] - 2 * C[(2, 0, 2)] + C[(0, 2, 2)], C[(2, 2, 0)] + C[(2, 0, 2)] - 2 * C[(0, 2, 2)])
+    g[7] = (C[(2, 2, 0)] + C[(2, 0, 2)] + C[(0, 2, 2)],)
+    g[8] = (C[(2, 1, 1)], C[(1, 2, 1)], C[(1, 1, 2)])
+    g[9] = (C[(2, 2, 1)], C[(2, 1, 2)], C[(1, 2, 2)])
+    g[10] = (C[(2, 2, 2)],)
+    return g
+
+
+@pytest.mark.parametrize("k", range(1, 11))
+def test_each_rate_relaxes_its_named_group(orc, k):
+    """omega_k = 1/2, all other rates 1: the group of omega_k keeps half of
+    its pre-collision value, every other group is at equilibrium. The ten
+    groups hold 23 independent combinations of the 23 cumulants of orders
+    2..6 (5+1+3+3+1+2+1+3+3+1), so together the ten cases fix the whole
+    assignment: exchanging two rates (e.g. the sums and differences of third
+    order, or the fourth-order trace and its differences) fails two of them."""
+    rng = np.random.default_rng(100 + k)
+    f = rand_pops(rng, rho=rng.uniform(0.9, 1.1), amp=0.45)
+    rho = f.sum()
+    u = (C27 * f[:, None]).sum(0) / rho
+    om = np.ones(10)
+    om[k - 1] = 0.5
+    fo = orc.collide(f, [0.0, 0.0, 0.0], om)
+    pre, post = _groups(_all_cumulants(f, u)), _groups(_all_cumulants(fo, u))
+    assert max(abs(v) for v in pre[k]) > 1e-5  # the group is really excited (tolerance 3e-15)
+    for g in range(1, 11):
+        for a, b in zip(pre[g], post[g]):
+            want = 0.5 * a if g == k else 0.0
+            assert b == pytest.approx(want, abs=3e-15), (k, g)
+
+
+def test_groups_cover_every_cumulant():
+    """The 23 group combinations are linearly independent over the 23
+    cumulants of orders 2..6, so the per-rate test above leaves no cumulant
+    unconstrained."""
+    keys = [(m % 3, (m // 3) % 3, m // 9) for m in range(27)]
+    keys = [key for key in keys if sum(key) >= 2]
+    rows = []
+    for key in keys:
+        C = {q: (1.0 if q == key else 0.0) for q in keys}
+        rows.append(np.concatenate([np.array(v, dtype=float) for _, v in sorted(_groups(C).items())]))
+    A = np.array(rows)
+    A[:, 5] += 1.0  # the trace group's offset of -1 is not linear; remove it
+    assert A.shape == (23, 23)
+    assert np.linalg.matrix_rank(A) == 23
+
+
+# ------------------------------------------------------------ inlet plane
+def test_inflow_plane_linear_ramp_closed_form():
+    """Frozen-box inlet (reading of the turbine-row inflow: a periodic box
+    convected through the inlet, Taylor's hypothesis). For a box that is an
+    affine ramp a + b s in the convected index s, the inlet at position
+    p = advect t is mean + a + b p inside [0, lt - 1]; between the last slice
+    and the wrap it interpolates towards slice 0; positions repeat with
+    period lt; without a box it is the mean."""
+    import oracle
+    rng = np.random.default_rng(21)
+    nz, ny, lt = 3, 4, 8
+    mean = rng.normal(0, 1, (3, nz, ny))
+    a = rng.normal(0, 1, (3, nz, ny))
+    b = rng.normal(0, 1, (3, nz, ny))
+    box = a[:, None] + b[:, None] * np.arange(lt)[None, :, None, None]
+    adv = 0.25
+    for p, want in ((0.0, mean + a), (2.25, mean + a + 2.25 * b), (5.0, mean + a + 5 * b),
+                    (6.75, mean + a + 6.75 * b),
+                    (7.5, mean + a + 0.5 * (7 * b)),          # half way from slice 7 back to slice 0
+                    (lt + 2.25, mean + a + 2.25 * b),        # one period later
+                    (3 * lt + 6.75, mean + a + 6.75 * b)):
+        got = oracle.inflow_plane(mean, box, adv, p / adv)
+        assert np.allclose(got, want, rtol=0, atol=1e-12), p
+    assert np.array_equal(oracle.inflow_plane(mean, None, adv, 17.0), mean)
+
+
+# ------------------------------------------------------------ network forward, hand-set weights
+def _handset_blob(j, p, q, mu, sigma, b1, b2, b3, w1, w2, w3, nu_scale):
+    """A network whose output depends on input feature j through hidden unit
+    p of layer 1 and unit q of layer 2 only: W1[p][j] = w1, W2[q][p] = w2,
+    w3[q] = w3; everything else zero."""
+    blob = np.zeros(mlp_ref.NBLOB)
+    s = mlp_ref.SL
+    W1 = np.zeros((32, 6))
+    W1[p, j] = w1
+    W2 = np.zeros((32, 32))
+    W2[q, p] = w2
+    bb1, bb2, ww3 = np.zeros(32), np.zeros(32), np.zeros(32)
+    bb1[p], bb2[q], ww3[q] = b1, b2, w3
+    blob[s["W1"][0]] = W1.reshape(-1)
+    blob[s["b1"][0]] = bb1
+    blob[s["W2"][0]] = W2.reshape(-1)
+    blob[s["b2"][0]] = bb2
+    blob[s["w3"][0]] = ww3
+    blob[s["b3"][0]] = b3
+    blob[s["mu"][0]] = mu
+    blob[s["sigma"][0]] = sigma
+    blob[s["nu_scale"][0]] = nu_scale
+    return blob
+
+
+@pytest.mark.parametrize("j,p,q", [(0, 0, 0), (1, 7, 3), (2, 31, 30), (3, 5, 17), (4, 12, 12), (5, 20, 1)])
+def test_mlp_forward_handset_closed_form(orc, j, p, q):
+    """nu_t = nu_s softplus(w3 max(0, w2 max(0, w1 (x_j - mu_j)/sigma_j + b1) + b2) + b3)
+    for the hand-set network, in both oracle modes (every value here is a
+    short dyadic fraction, exact in bfloat16, so the emulating mode gives the
+    same closed form). A transposed W1 or W2, a wrong hidden index, a dropped
+    bias or a missing ReLU changes the result."""
+    mu, sigma = np.full(6, 0.25), np.full(6, 0.5)   # 1/sigma = 2 exactly
+    w1, w2, w3, b1, b2, b3, nus = 2.0, 0.5, 1.5, 0.5, 0.25, -1.0, 0.75
+    blob = _handset_blob(j, p, q, mu, sigma, b1, b2, b3, w1, w2, w3, nus)
+    for xj in (1.75, 0.5, -1.0, 0.25, 3.0):
+        x = np.full(6, 4.0)       # the other features must not matter
+        x[j] = xj
+        xh = (xj - 0.25) / 0.5
+        h1 = max(0.0, w1 * xh + b1)
+        h2 = max(0.0, w2 * h1 + b2)
+        z = w3 * h2 + b3
+        want = nus * math.log1p(math.exp(z))
+        for emu in (False, True):
+            assert orc.mlp_nu_t(blob, x, emu) == pytest.approx(want, rel=1e-15), (xj, emu)
+            nu, _ = mlp_ref.forward(blob, x[None, :], emulate_bf16=emu)
+            assert nu[0] == pytest.approx(want, rel=1e-15), (xj, emu)
