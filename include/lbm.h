@@ -317,9 +317,12 @@ const char *lbm_mlp_last_error(const lbm_mlp *m);
 /* Checkpoint: raw population store, outflow ghost plane, time, layout
  * parity and the force boxes of the rotor and turbine slots (the spread
  * force of the last step, half of which the next step's sampled velocity
- * includes). lbm_state_bytes gives the size. Restore into a context with the
- * same configuration and the same rotors and turbines set (else
- * LBM_EINVAL). Synchronises. */
+ * includes), behind a header that records the grid shape and storage type.
+ * lbm_state_bytes gives the size. Restore into a context with the same
+ * configuration and the same rotors and turbines set: a state of another
+ * grid shape (even with the same cell count), another storage type or other
+ * force boxes gives LBM_EINVAL, checked before any device work.
+ * Synchronises. */
 int lbm_state_bytes(const lbm_ctx *ctx, size_t *bytes);
 int lbm_get_state(lbm_ctx *ctx, void *host_buf, size_t bytes);
 int lbm_set_state(lbm_ctx *ctx, const void *host_buf, size_t bytes);

@@ -302,6 +302,31 @@ int mfail(lbm_mlp *m, int code, const char *msg) {
         if (e_ != hipSuccess) return mfail(m, LBM_EHIP, hipGetErrorString(e_)); \
     } while (0)
 
+// No exception crosses the C ABI (the error string is the only host
+// allocation here): a failure returns LBM_ENOMEM or LBM_EINVAL.
+template <typename F>
+int guard(const lbm_mlp *cm, F &&body) noexcept {
+    lbm_mlp *m = const_cast<lbm_mlp *>(cm);
+    int code;
+    const char *msg;
+    try {
+        return body();
+    } catch (const std::bad_alloc &) {
+        code = LBM_ENOMEM;
+        msg = "host allocation failed";
+    } catch (...) {
+        code = LBM_EINVAL;
+        msg = "unexpected host error";
+    }
+    if (m) {
+        try {
+            m->err = msg;
+        } catch (...) {
+        }
+    }
+    return code;
+}
+
 int ensure_waves(lbm_mlp *m, size_t nw) {
     if (nw <= m->cap_waves) return LBM_OK;
     if (m->d_part) (void)hipFree(m->d_part);
@@ -320,127 +345,143 @@ int ensure_waves(lbm_mlp *m, size_t nw) {
 extern "C" {
 
 int lbm_mlp_create(void *stream, lbm_mlp **out) {
-    if (!out) return LBM_EINVAL;
-    *out = nullptr;
-    lbm_mlp *m = new (std::nothrow) lbm_mlp();
-    if (!m) return LBM_ENOMEM;
-    if (stream) {
-        m->stream = (hipStream_t)stream;
-    } else if (hipStreamCreate(&m->stream) != hipSuccess) {
-        delete m;
-        return LBM_EHIP;
-    } else {
-        m->own_stream = true;
-    }
-    bool ok = hipMalloc((void **)&m->d_M, sizeof(MlpDev)) == hipSuccess &&
-              hipMalloc((void **)&m->d_params, MLP_NPARAM * sizeof(float)) == hipSuccess &&
-              hipMalloc((void **)&m->d_m, MLP_NPARAM * sizeof(float)) == hipSuccess &&
-              hipMalloc((void **)&m->d_v, MLP_NPARAM * sizeof(float)) == hipSuccess &&
-              hipMalloc((void **)&m->d_grad, MLP_NPARAM * sizeof(float)) == hipSuccess &&
-              hipMalloc((void **)&m->d_loss, 2 * sizeof(double)) == hipSuccess &&
-              hipMalloc((void **)&m->d_groups, (size_t)RED_GROUPS * (MLP_NPARAM + 1) * sizeof(double)) == hipSuccess;
-    if (!ok || hipMemsetAsync(m->d_loss, 0, 2 * sizeof(double), m->stream) != hipSuccess) {
-        lbm_mlp_destroy(m);
-        return LBM_ENOMEM;
-    }
-    *out = m;
-    return LBM_OK;
+    return guard(nullptr, [&]() -> int {
+        if (!out) return LBM_EINVAL;
+        *out = nullptr;
+        lbm_mlp *m = new (std::nothrow) lbm_mlp();
+        if (!m) return LBM_ENOMEM;
+        if (stream) {
+            m->stream = (hipStream_t)stream;
+        } else if (hipStreamCreate(&m->stream) != hipSuccess) {
+            delete m;
+            return LBM_EHIP;
+        } else {
+            m->own_stream = true;
+        }
+        bool ok = hipMalloc((void **)&m->d_M, sizeof(MlpDev)) == hipSuccess &&
+                  hipMalloc((void **)&m->d_params, MLP_NPARAM * sizeof(float)) == hipSuccess &&
+                  hipMalloc((void **)&m->d_m, MLP_NPARAM * sizeof(float)) == hipSuccess &&
+                  hipMalloc((void **)&m->d_v, MLP_NPARAM * sizeof(float)) == hipSuccess &&
+                  hipMalloc((void **)&m->d_grad, MLP_NPARAM * sizeof(float)) == hipSuccess &&
+                  hipMalloc((void **)&m->d_loss, 2 * sizeof(double)) == hipSuccess &&
+                  hipMalloc((void **)&m->d_groups, (size_t)RED_GROUPS * (MLP_NPARAM + 1) * sizeof(double)) == hipSuccess;
+        if (!ok || hipMemsetAsync(m->d_loss, 0, 2 * sizeof(double), m->stream) != hipSuccess) {
+            lbm_mlp_destroy(m);
+            return LBM_ENOMEM;
+        }
+        *out = m;
+        return LBM_OK;
+    });
 }
 
 int lbm_mlp_destroy(lbm_mlp *m) {
-    if (!m) return LBM_EINVAL;
-    if (m->stream) (void)hipStreamSynchronize(m->stream);
-    void *ptrs[] = {m->d_M, m->d_params, m->d_m, m->d_v, m->d_grad, m->d_part, m->d_lpart, m->d_loss, m->d_groups};
-    for (void *p : ptrs)
-        if (p) (void)hipFree(p);
-    if (m->own_stream) (void)hipStreamDestroy(m->stream);
-    delete m;
-    return LBM_OK;
+    return guard(m, [&]() -> int {
+        if (!m) return LBM_EINVAL;
+        if (m->stream) (void)hipStreamSynchronize(m->stream);
+        void *ptrs[] = {m->d_M, m->d_params, m->d_m, m->d_v, m->d_grad, m->d_part, m->d_lpart, m->d_loss, m->d_groups};
+        for (void *p : ptrs)
+            if (p) (void)hipFree(p);
+        if (m->own_stream) (void)hipStreamDestroy(m->stream);
+        delete m;
+        return LBM_OK;
+    });
 }
 
 int lbm_mlp_set_params(lbm_mlp *m, const float *blob, size_t n) {
-    if (!m) return LBM_EINVAL;
-    if (!blob || n != (size_t)MLP_NBLOB) return mfail(m, LBM_EINVAL, "expected 1326 parameters");
-    for (int j = 0; j < 6; ++j)
-        if (!(blob[O_SG + j] > 0.0f)) return mfail(m, LBM_EINVAL, "sigma must be positive");
-    MlpDev h;
-    mlp_pack(blob, &h);
-    MCHK(m, hipMemcpyAsync(m->d_M, &h, sizeof h, hipMemcpyHostToDevice, m->stream));
-    MCHK(m, hipMemcpyAsync(m->d_params, blob, MLP_NPARAM * sizeof(float), hipMemcpyHostToDevice, m->stream));
-    MCHK(m, hipMemsetAsync(m->d_m, 0, MLP_NPARAM * sizeof(float), m->stream));
-    MCHK(m, hipMemsetAsync(m->d_v, 0, MLP_NPARAM * sizeof(float), m->stream));
-    MCHK(m, hipStreamSynchronize(m->stream));
-    std::memcpy(m->blob_tail, blob + MLP_NPARAM, sizeof m->blob_tail);
-    m->step = 0;
-    m->has_params = true;
-    m->has_grad = false;
-    return LBM_OK;
+    return guard(m, [&]() -> int {
+        if (!m) return LBM_EINVAL;
+        if (!blob || n != (size_t)MLP_NBLOB) return mfail(m, LBM_EINVAL, "expected 1326 parameters");
+        for (int j = 0; j < 6; ++j)
+            if (!(blob[O_SG + j] > 0.0f)) return mfail(m, LBM_EINVAL, "sigma must be positive");
+        MlpDev h;
+        mlp_pack(blob, &h);
+        MCHK(m, hipMemcpyAsync(m->d_M, &h, sizeof h, hipMemcpyHostToDevice, m->stream));
+        MCHK(m, hipMemcpyAsync(m->d_params, blob, MLP_NPARAM * sizeof(float), hipMemcpyHostToDevice, m->stream));
+        MCHK(m, hipMemsetAsync(m->d_m, 0, MLP_NPARAM * sizeof(float), m->stream));
+        MCHK(m, hipMemsetAsync(m->d_v, 0, MLP_NPARAM * sizeof(float), m->stream));
+        MCHK(m, hipStreamSynchronize(m->stream));
+        std::memcpy(m->blob_tail, blob + MLP_NPARAM, sizeof m->blob_tail);
+        m->step = 0;
+        m->has_params = true;
+        m->has_grad = false;
+        return LBM_OK;
+    });
 }
 
 int lbm_mlp_get_params(lbm_mlp *m, float *blob, size_t n) {
-    if (!m) return LBM_EINVAL;
-    if (!blob || n != (size_t)MLP_NBLOB) return mfail(m, LBM_EINVAL, "expected 1326 parameters");
-    if (!m->has_params) return mfail(m, LBM_ESTATE, "parameters not set");
-    MCHK(m, hipMemcpyAsync(blob, m->d_params, MLP_NPARAM * sizeof(float), hipMemcpyDeviceToHost, m->stream));
-    MCHK(m, hipStreamSynchronize(m->stream));
-    std::memcpy(blob + MLP_NPARAM, m->blob_tail, sizeof m->blob_tail);
-    return LBM_OK;
+    return guard(m, [&]() -> int {
+        if (!m) return LBM_EINVAL;
+        if (!blob || n != (size_t)MLP_NBLOB) return mfail(m, LBM_EINVAL, "expected 1326 parameters");
+        if (!m->has_params) return mfail(m, LBM_ESTATE, "parameters not set");
+        MCHK(m, hipMemcpyAsync(blob, m->d_params, MLP_NPARAM * sizeof(float), hipMemcpyDeviceToHost, m->stream));
+        MCHK(m, hipStreamSynchronize(m->stream));
+        std::memcpy(blob + MLP_NPARAM, m->blob_tail, sizeof m->blob_tail);
+        return LBM_OK;
+    });
 }
 
 int lbm_mlp_forward(lbm_mlp *m, const float *d_feat, size_t count, float *d_nu) {
-    if (!m) return LBM_EINVAL;
-    if (!m->has_params) return mfail(m, LBM_ESTATE, "parameters not set");
-    if (count == 0) return LBM_OK;
-    if (!d_feat || !d_nu) return mfail(m, LBM_EINVAL, "null device array");
-    k_mlp_forward<<<(unsigned)((count + TB - 1) / TB), TB, 0, m->stream>>>(m->d_M, d_feat, count, d_nu);
-    MCHK(m, hipGetLastError());
-    return LBM_OK;
+    return guard(m, [&]() -> int {
+        if (!m) return LBM_EINVAL;
+        if (!m->has_params) return mfail(m, LBM_ESTATE, "parameters not set");
+        if (count == 0) return LBM_OK;
+        if (!d_feat || !d_nu) return mfail(m, LBM_EINVAL, "null device array");
+        k_mlp_forward<<<(unsigned)((count + TB - 1) / TB), TB, 0, m->stream>>>(m->d_M, d_feat, count, d_nu);
+        MCHK(m, hipGetLastError());
+        return LBM_OK;
+    });
 }
 
 int lbm_mlp_loss_grad(lbm_mlp *m, const float *d_feat, const float *d_target, size_t count, float *grad) {
-    if (!m) return LBM_EINVAL;
-    if (!m->has_params) return mfail(m, LBM_ESTATE, "parameters not set");
-    if (count == 0 || !d_feat || !d_target) return mfail(m, LBM_EINVAL, "empty batch or null device array");
-    const size_t nw = (count + GW - 1) / GW;
-    int rc = ensure_waves(m, nw);
-    if (rc) return rc;
-    k_mlp_grad<<<(unsigned)nw, GW, 0, m->stream>>>(m->d_M, d_feat, d_target, count, 1.0f / (float)count, m->d_part,
-                                                   m->d_lpart);
-    const int per = (int)((nw + RED_GROUPS - 1) / RED_GROUPS), ngroups = (int)((nw + per - 1) / per);
-    const unsigned pblocks = (MLP_NPARAM + 1 + TB - 1) / TB;
-    k_mlp_reduce_groups<<<dim3(pblocks, ngroups), TB, 0, m->stream>>>(m->d_part, m->d_lpart, (int)nw, per,
-                                                                      m->d_groups);
-    k_mlp_reduce<<<pblocks, TB, 0, m->stream>>>(m->d_groups, ngroups, m->d_grad, (double)count, m->d_loss);
-    MCHK(m, hipGetLastError());
-    m->has_grad = true;
-    if (grad) {
-        MCHK(m, hipMemcpyAsync(grad, m->d_grad, MLP_NPARAM * sizeof(float), hipMemcpyDeviceToHost, m->stream));
-        MCHK(m, hipStreamSynchronize(m->stream));
-    }
-    return LBM_OK;
+    return guard(m, [&]() -> int {
+        if (!m) return LBM_EINVAL;
+        if (!m->has_params) return mfail(m, LBM_ESTATE, "parameters not set");
+        if (count == 0 || !d_feat || !d_target) return mfail(m, LBM_EINVAL, "empty batch or null device array");
+        const size_t nw = (count + GW - 1) / GW;
+        int rc = ensure_waves(m, nw);
+        if (rc) return rc;
+        k_mlp_grad<<<(unsigned)nw, GW, 0, m->stream>>>(m->d_M, d_feat, d_target, count, 1.0f / (float)count, m->d_part,
+                                                       m->d_lpart);
+        const int per = (int)((nw + RED_GROUPS - 1) / RED_GROUPS), ngroups = (int)((nw + per - 1) / per);
+        const unsigned pblocks = (MLP_NPARAM + 1 + TB - 1) / TB;
+        k_mlp_reduce_groups<<<dim3(pblocks, ngroups), TB, 0, m->stream>>>(m->d_part, m->d_lpart, (int)nw, per,
+                                                                          m->d_groups);
+        k_mlp_reduce<<<pblocks, TB, 0, m->stream>>>(m->d_groups, ngroups, m->d_grad, (double)count, m->d_loss);
+        MCHK(m, hipGetLastError());
+        m->has_grad = true;
+        if (grad) {
+            MCHK(m, hipMemcpyAsync(grad, m->d_grad, MLP_NPARAM * sizeof(float), hipMemcpyDeviceToHost, m->stream));
+            MCHK(m, hipStreamSynchronize(m->stream));
+        }
+        return LBM_OK;
+    });
 }
 
 int lbm_mlp_adam_step(lbm_mlp *m, float lr, float beta1, float beta2, float eps) {
-    if (!m) return LBM_EINVAL;
-    if (!m->has_grad) return mfail(m, LBM_ESTATE, "no gradient computed");
-    if (!(lr > 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps >= 0.0f))
-        return mfail(m, LBM_EINVAL, "bad Adam hyper-parameters");
-    m->step += 1;
-    k_mlp_adam<<<(MLP_NPARAM + TB - 1) / TB, TB, 0, m->stream>>>(m->d_params, m->d_grad, m->d_m, m->d_v, m->step, lr,
-                                                                 beta1, beta2, eps);
-    k_mlp_refresh<<<1, TB, 0, m->stream>>>(m->d_params, m->d_M);
-    MCHK(m, hipGetLastError());
-    return LBM_OK;
+    return guard(m, [&]() -> int {
+        if (!m) return LBM_EINVAL;
+        if (!m->has_grad) return mfail(m, LBM_ESTATE, "no gradient computed");
+        if (!(lr > 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps >= 0.0f))
+            return mfail(m, LBM_EINVAL, "bad Adam hyper-parameters");
+        m->step += 1;
+        k_mlp_adam<<<(MLP_NPARAM + TB - 1) / TB, TB, 0, m->stream>>>(m->d_params, m->d_grad, m->d_m, m->d_v, m->step, lr,
+                                                                     beta1, beta2, eps);
+        k_mlp_refresh<<<1, TB, 0, m->stream>>>(m->d_params, m->d_M);
+        MCHK(m, hipGetLastError());
+        return LBM_OK;
+    });
 }
 
 int lbm_mlp_take_loss(lbm_mlp *m, double *mean_loss) {
-    if (!m || !mean_loss) return LBM_EINVAL;
-    double h[2];
-    MCHK(m, hipMemcpyAsync(h, m->d_loss, 2 * sizeof(double), hipMemcpyDeviceToHost, m->stream));
-    MCHK(m, hipStreamSynchronize(m->stream));
-    MCHK(m, hipMemsetAsync(m->d_loss, 0, 2 * sizeof(double), m->stream));
-    *mean_loss = h[1] > 0 ? h[0] / h[1] : 0.0;
-    return LBM_OK;
+    return guard(m, [&]() -> int {
+        if (!m || !mean_loss) return LBM_EINVAL;
+        double h[2];
+        MCHK(m, hipMemcpyAsync(h, m->d_loss, 2 * sizeof(double), hipMemcpyDeviceToHost, m->stream));
+        MCHK(m, hipStreamSynchronize(m->stream));
+        MCHK(m, hipMemsetAsync(m->d_loss, 0, 2 * sizeof(double), m->stream));
+        *mean_loss = h[1] > 0 ? h[0] / h[1] : 0.0;
+        return LBM_OK;
+    });
 }
 
 const char *lbm_mlp_last_error(const lbm_mlp *m) { return m ? m->err.c_str() : "null handle"; }

@@ -430,8 +430,18 @@ class Lbm:
 def copy_probe(src, dst, stream=None):
     """Device copy src -> dst (torch CUDA tensors of equal byte size) with the
     library's streaming copy kernel on `stream` (a torch stream)."""
+    # the kernel reads and writes numel * element_size bytes from the base
+    # pointers: both must be whole device buffers on one device
+    for name, t in (("src", src), ("dst", dst)):
+        if not t.is_cuda:
+            raise ValueError(f"copy_probe: {name} is not a device tensor")
+        if not t.is_contiguous():
+            raise ValueError(f"copy_probe: {name} is not contiguous")
+    if src.device != dst.device:
+        raise ValueError("copy_probe: src and dst are on different devices")
     nbytes = src.numel() * src.element_size()
-    assert dst.numel() * dst.element_size() == nbytes
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("copy_probe: src and dst differ in size")
     h = stream.cuda_stream if stream is not None else None
     rc = lib().lbm_copy_probe(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), nbytes,
                               C.c_void_p(h) if h else None)

@@ -74,3 +74,56 @@ def test_copy_probe_validates_before_any_device_work():
     assert L.lbm_copy_probe(vp(264), vp(512), 4096, None) == lbm.EINVAL   # source not 16-byte aligned
     assert L.lbm_copy_probe(vp(256), vp(520), 4096, None) == lbm.EINVAL   # destination not 16-byte aligned
     assert L.lbm_copy_probe(vp(256), vp(512), 0, None) == lbm.OK          # nothing to copy: no launch
+
+
+def _unattached_context(nx, ny, nz, storage=0):
+    """A context with a placeholder stream handle: lbm_create stores it and
+    makes no HIP call; nothing here enqueues work on it."""
+    from paper_2402_13171_amd import lbm
+    L = lbm.lib()
+    cfg = lbm.Config()
+    cfg.nx, cfg.ny, cfg.nz = nx, ny, nz
+    cfg.omega = 1.9
+    cfg.storage = storage
+    cfg.stream = ctypes.c_void_p(0x1000)
+    h = ctypes.c_void_p()
+    assert L.lbm_create(ctypes.byref(cfg), ctypes.byref(h)) == lbm.OK
+    return L, h
+
+
+def test_state_of_another_shape_or_storage_is_refused_before_device_work():
+    """The checkpoint header (eight int64: magic, time, parity, storage,
+    force-box bytes, nx, ny, nz) is checked before the context is even
+    attached: a state of the same cell count but another grid shape, or of
+    another storage type, gives LBM_EINVAL."""
+    import numpy as np
+    from paper_2402_13171_amd import lbm
+    L, h = _unattached_context(16, 32, 8)
+    try:
+        nb = ctypes.c_size_t()
+        assert L.lbm_state_bytes(h, ctypes.byref(nb)) == lbm.OK
+        buf = np.zeros(nb.value, dtype=np.uint8)
+        hdr = buf[:64].view(np.int64)
+        hdr[:8] = [0x4c424d32, 5, 1, 0, 0, 32, 16, 8]       # a 32 x 16 x 8 grid: same cell count
+        vp = ctypes.c_void_p(buf.ctypes.data)
+        assert L.lbm_set_state(h, vp, nb.value) == lbm.EINVAL
+        assert b"32x16x8" in L.lbm_last_error(h)
+        hdr[:8] = [0x4c424d32, 5, 1, 1, 0, 16, 32, 8]       # FP16 state into an FP32 context
+        assert L.lbm_set_state(h, vp, nb.value) == lbm.EINVAL
+        assert b"storage" in L.lbm_last_error(h)
+        hdr[:8] = [0x4c424d31, 5, 1, 0, 0, 16, 32, 8]       # not this library's header
+        assert L.lbm_set_state(h, vp, nb.value) == lbm.EINVAL
+        assert L.lbm_set_state(h, vp, nb.value - 1) == lbm.EINVAL   # short buffer
+        # a matching header passes the header checks and stops at the attach check
+        hdr[:8] = [0x4c424d32, 5, 1, 0, 0, 16, 32, 8]
+        assert L.lbm_set_state(h, vp, nb.value) == lbm.ESTATE
+    finally:
+        assert L.lbm_destroy(h) == lbm.OK
+
+
+def test_copy_probe_binding_rejects_host_tensors():
+    import torch
+    from paper_2402_13171_amd import lbm
+    a, b = torch.zeros(64), torch.zeros(64)
+    with pytest.raises(ValueError, match="not a device tensor"):
+        lbm.copy_probe(a, b)

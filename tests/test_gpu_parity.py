@@ -197,6 +197,27 @@ def test_checkpoint_roundtrip_is_bitwise():
     assert np.array_equal(b.pops(), f1)
 
 
+def test_checkpoint_of_another_grid_shape_is_refused():
+    """A state of a 32 x 16 x 8 grid has the byte size of a 16 x 32 x 8 one;
+    the header's grid shape makes the restore fail, and the target context
+    is left as it was."""
+    _need_gpu()
+    from paper_2402_13171_amd.lbm import Lbm, LbmError, EINVAL
+    a = Lbm(32, 16, 8, omega=1.9)
+    b = Lbm(16, 32, 8, omega=1.9)
+    a.init_tgv(0.05)
+    b.init_tgv(0.03)
+    a.step(3)
+    b.step(2)
+    state = a.get_state()
+    assert len(state) == len(b.get_state())
+    before = b.pops()
+    with pytest.raises(LbmError) as ei:
+        b.set_state(state)
+    assert ei.value.code == EINVAL
+    assert b.time == 2 and np.array_equal(b.pops(), before)
+
+
 @pytest.mark.parametrize("storage", ["f32", "f16"])
 def test_pattern_probe_is_an_involution(storage):
     """The access-pattern probe moves every value to the slot the collision

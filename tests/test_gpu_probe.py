@@ -25,3 +25,22 @@ def test_copy_probe_is_an_exact_copy(nbytes):
     out = dst.cpu().numpy()
     assert np.array_equal(out[:nbytes], src_h.numpy())
     assert np.all(out[nbytes:] == 0xA5)
+
+
+def test_copy_probe_binding_rejects_strided_and_mismatched_views():
+    """The kernel copies numel * element_size bytes from the base pointers, so
+    the binding refuses views that do not cover that range contiguously."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2402_13171_amd.lbm import copy_probe
+    a = torch.zeros((64, 64), device="cuda")
+    b = torch.zeros((64, 64), device="cuda")
+    with pytest.raises(ValueError, match="not contiguous"):
+        copy_probe(a.t(), b)
+    with pytest.raises(ValueError, match="not contiguous"):
+        copy_probe(a, b[:, ::2].repeat(1, 2)[:, ::2].t())
+    with pytest.raises(ValueError, match="differ in size"):
+        copy_probe(a, b[:32])
+    with pytest.raises(ValueError, match="not a device tensor"):
+        copy_probe(a, torch.zeros((64, 64)))
