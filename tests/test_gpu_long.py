@@ -1,10 +1,12 @@
-"""Long GPU <-> oracle runs, opt-in (set LBM_LONG_TESTS=1): the single-turbine
-case over 2000 steps (about seven rotor revolutions), thrust, torque and
-power time series against the FP64 oracle (about four minutes of oracle
-time on 16 host cores); a floating turbine tree (tower, nacelle, rotor on a
-pitching and surging platform) over 2000 steps, five platform periods (about
-five minutes); and the 512^3 headline box over 200 steps with FP32, FP16 and
-BF16 storage (about fourteen minutes)."""
+"""Long GPU <-> oracle runs. In the suite: the single-turbine case over 2000
+steps (about seven rotor revolutions), thrust, torque and power time series
+against the FP64 oracle (about four minutes of oracle time on 16 host
+cores), and the reduced turbine-row case with the learned closure over 1000
+steps (about half a minute). Opt-in (set LBM_LONG_TESTS=1): a floating
+turbine tree (tower, nacelle, rotor on a pitching and surging platform) over
+2000 steps, five platform periods (about five minutes), and the 512^3
+headline box over 200 steps with FP32, FP16 and BF16 storage (about fourteen
+minutes and 60 GB of host memory)."""
 import os
 
 import numpy as np
@@ -14,9 +16,9 @@ import oracle
 import workloads
 from workloads import turbines as TB
 
-pytestmark = [pytest.mark.gpu,
-              pytest.mark.skipif(not os.environ.get("LBM_LONG_TESTS"),
-                                 reason="long runs (4, 5 and 14 min of FP64 oracle time); set LBM_LONG_TESTS=1")]
+pytestmark = pytest.mark.gpu
+opt_in = pytest.mark.skipif(not os.environ.get("LBM_LONG_TESTS"),
+                            reason="long run (5 or 14 min of FP64 oracle time); set LBM_LONG_TESTS=1")
 
 
 def test_single_turbine_loads_over_2000_steps():
@@ -55,6 +57,7 @@ def test_single_turbine_loads_over_2000_steps():
     assert err <= 1e-3
 
 
+@opt_in
 def test_floating_turbine_tree_over_2000_steps():
     """Sec. 3.3 tree on a moving platform: the floating configuration of the
     turbine-tree runs (pitch 0.05 rad and surge 1 cell at a 400-step wave
@@ -151,6 +154,7 @@ def test_closure_row_analogue_over_1000_steps():
     assert err["f16"] <= 2e-2
 
 
+@opt_in
 def test_storage_errors_512_full_box_200_steps():
     """The headline workload itself: the 512^3 random-phase box, 200 steps,
     FP32 / FP16 / BF16 storage against the FP64 oracle on the whole box and

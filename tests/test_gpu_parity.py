@@ -198,13 +198,13 @@ def test_checkpoint_roundtrip_is_bitwise():
 
 
 def test_checkpoint_of_another_grid_shape_is_refused():
-    """A state of a 32 x 16 x 8 grid has the byte size of a 16 x 32 x 8 one;
-    the header's grid shape makes the restore fail, and the target context
-    is left as it was."""
+    """A state of a 16 x 32 x 8 grid has the byte size of a 16 x 8 x 32 one
+    (same cell count, same ny nz for the ghost plane); the header's grid shape
+    makes the restore fail, and the target context is left as it was."""
     _need_gpu()
     from paper_2402_13171_amd.lbm import Lbm, LbmError, EINVAL
-    a = Lbm(32, 16, 8, omega=1.9)
-    b = Lbm(16, 32, 8, omega=1.9)
+    a = Lbm(16, 32, 8, omega=1.9)
+    b = Lbm(16, 8, 32, omega=1.9)
     a.init_tgv(0.05)
     b.init_tgv(0.03)
     a.step(3)
