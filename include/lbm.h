@@ -308,6 +308,18 @@ int lbm_mlp_forward(lbm_mlp *m, const float *d_feat, size_t count, float *d_nu);
  * copied to host grad[1313] when grad is not NULL, which synchronises). The
  * batch loss is added to an accumulator read by lbm_mlp_take_loss. */
 int lbm_mlp_loss_grad(lbm_mlp *m, const float *d_feat, const float *d_target, size_t count, float *grad);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight training loops, harnesses that forbid hipMalloc): the same
+ * loss and gradient as lbm_mlp_loss_grad, bit for bit, with the per-wave
+ * partials in a static device array of the library instead of a buffer the
+ * trainer allocates as batches grow. Calls no hipMalloc or hipFree. At most
+ * 65536 samples per call (5.4 MB of scratch per device, held until the
+ * process ends); larger batches return LBM_EINVAL before any device work, as
+ * does a current device other than the one the trainer was created on.
+ * Every call on one device shares that device's scratch: calls that overlap
+ * in time on one device (two trainers on different streams) race and must be
+ * ordered by the caller. */
+int lbm_mlp_loss_grad_noalloc(lbm_mlp *m, const float *d_feat, const float *d_target, size_t count, float *grad);
 /* One Adam update (Kingma and Ba 2015) with the last gradient. */
 int lbm_mlp_adam_step(lbm_mlp *m, float lr, float beta1, float beta2, float eps);
 /* Mean loss over the batches since the last call; resets. Synchronises. */

@@ -18,6 +18,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -273,9 +274,41 @@ __global__ __launch_bounds__(TB) void k_mlp_refresh(const float *params, MlpDev 
     }
 }
 
+// Scratch of lbm_mlp_loss_grad_noalloc: the per-wave gradient partials
+// (float, MLP_NPARAM per wave) followed by the per-wave loss partials
+// (double) for batches of up to NOALLOC_MAX_COUNT samples (5.4 MB). One copy
+// per device, held until the process ends. Host code never passes the
+// array's name to a kernel: it takes the device address of this device's
+// copy from hipGetSymbolAddress (noalloc_scratch below).
+constexpr size_t NOALLOC_MAX_COUNT = 65536;
+constexpr size_t NOALLOC_MAX_WAVES = NOALLOC_MAX_COUNT / GW;
+constexpr size_t NOALLOC_PART_FLOATS = NOALLOC_MAX_WAVES * MLP_NPARAM;  // even: the doubles stay 8-byte aligned
+static __device__ __align__(256) float scratch[NOALLOC_PART_FLOATS + 2 * NOALLOC_MAX_WAVES];
+
 }  // namespace lbm
 
 using namespace lbm;
+
+namespace {
+// Device address of the scratch array, looked up once per device with that
+// device current.
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+float *g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+int noalloc_scratch(float **out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= NOALLOC_MAX_DEVICES) return LBM_EHIP;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return LBM_EHIP;
+        g_scratch_ptr[dev] = (float *)ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return LBM_OK;
+}
+}  // namespace
 
 struct lbm_mlp {
     hipStream_t stream = nullptr;
@@ -284,6 +317,8 @@ struct lbm_mlp {
     float *d_params = nullptr, *d_m = nullptr, *d_v = nullptr, *d_grad = nullptr, *d_part = nullptr;
     double *d_lpart = nullptr, *d_loss = nullptr, *d_groups = nullptr;
     size_t cap_waves = 0;
+    float *d_scratch = nullptr;  // this device's copy of lbm::scratch
+    int dev = -1;                // device current at creation
     float blob_tail[13] = {0};
     int step = 0;
     bool has_params = false;
@@ -369,6 +404,10 @@ int lbm_mlp_create(void *stream, lbm_mlp **out) {
             lbm_mlp_destroy(m);
             return LBM_ENOMEM;
         }
+        if (hipGetDevice(&m->dev) != hipSuccess || noalloc_scratch(&m->d_scratch) != LBM_OK) {
+            lbm_mlp_destroy(m);
+            return LBM_EHIP;
+        }
         *out = m;
         return LBM_OK;
     });
@@ -432,6 +471,30 @@ int lbm_mlp_forward(lbm_mlp *m, const float *d_feat, size_t count, float *d_nu) 
     });
 }
 
+}  // extern "C"
+
+namespace {
+// Gradient kernels of one batch with the per-wave partials in part / lpart
+// (room for nw waves each).
+int loss_grad_launch(lbm_mlp *m, const float *d_feat, const float *d_target, size_t count, size_t nw, float *part,
+                     double *lpart, float *grad) {
+    k_mlp_grad<<<(unsigned)nw, GW, 0, m->stream>>>(m->d_M, d_feat, d_target, count, 1.0f / (float)count, part, lpart);
+    const int per = (int)((nw + RED_GROUPS - 1) / RED_GROUPS), ngroups = (int)((nw + per - 1) / per);
+    const unsigned pblocks = (MLP_NPARAM + 1 + TB - 1) / TB;
+    k_mlp_reduce_groups<<<dim3(pblocks, ngroups), TB, 0, m->stream>>>(part, lpart, (int)nw, per, m->d_groups);
+    k_mlp_reduce<<<pblocks, TB, 0, m->stream>>>(m->d_groups, ngroups, m->d_grad, (double)count, m->d_loss);
+    MCHK(m, hipGetLastError());
+    m->has_grad = true;
+    if (grad) {
+        MCHK(m, hipMemcpyAsync(grad, m->d_grad, MLP_NPARAM * sizeof(float), hipMemcpyDeviceToHost, m->stream));
+        MCHK(m, hipStreamSynchronize(m->stream));
+    }
+    return LBM_OK;
+}
+}  // namespace
+
+extern "C" {
+
 int lbm_mlp_loss_grad(lbm_mlp *m, const float *d_feat, const float *d_target, size_t count, float *grad) {
     return guard(m, [&]() -> int {
         if (!m) return LBM_EINVAL;
@@ -440,20 +503,24 @@ int lbm_mlp_loss_grad(lbm_mlp *m, const float *d_feat, const float *d_target, si
         const size_t nw = (count + GW - 1) / GW;
         int rc = ensure_waves(m, nw);
         if (rc) return rc;
-        k_mlp_grad<<<(unsigned)nw, GW, 0, m->stream>>>(m->d_M, d_feat, d_target, count, 1.0f / (float)count, m->d_part,
-                                                       m->d_lpart);
-        const int per = (int)((nw + RED_GROUPS - 1) / RED_GROUPS), ngroups = (int)((nw + per - 1) / per);
-        const unsigned pblocks = (MLP_NPARAM + 1 + TB - 1) / TB;
-        k_mlp_reduce_groups<<<dim3(pblocks, ngroups), TB, 0, m->stream>>>(m->d_part, m->d_lpart, (int)nw, per,
-                                                                          m->d_groups);
-        k_mlp_reduce<<<pblocks, TB, 0, m->stream>>>(m->d_groups, ngroups, m->d_grad, (double)count, m->d_loss);
-        MCHK(m, hipGetLastError());
-        m->has_grad = true;
-        if (grad) {
-            MCHK(m, hipMemcpyAsync(grad, m->d_grad, MLP_NPARAM * sizeof(float), hipMemcpyDeviceToHost, m->stream));
-            MCHK(m, hipStreamSynchronize(m->stream));
-        }
-        return LBM_OK;
+        return loss_grad_launch(m, d_feat, d_target, count, nw, m->d_part, m->d_lpart, grad);
+    });
+}
+
+int lbm_mlp_loss_grad_noalloc(lbm_mlp *m, const float *d_feat, const float *d_target, size_t count, float *grad) {
+    return guard(m, [&]() -> int {
+        if (!m) return LBM_EINVAL;
+        if (!m->has_params) return mfail(m, LBM_ESTATE, "parameters not set");
+        if (count == 0 || !d_feat || !d_target) return mfail(m, LBM_EINVAL, "empty batch or null device array");
+        if (count > NOALLOC_MAX_COUNT)
+            return mfail(m, LBM_EINVAL, "batch exceeds the 65536 samples of the no-allocation scratch");
+        int dev = -1;
+        if (hipGetDevice(&dev) != hipSuccess) return mfail(m, LBM_EHIP, "hipGetDevice failed");
+        if (dev != m->dev)
+            return mfail(m, LBM_EINVAL, "current device is not the trainer's device");
+        const size_t nw = (count + GW - 1) / GW;
+        return loss_grad_launch(m, d_feat, d_target, count, nw, m->d_scratch,
+                                (double *)(m->d_scratch + NOALLOC_PART_FLOATS), grad);
     });
 }
 

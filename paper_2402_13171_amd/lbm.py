@@ -27,7 +27,7 @@ EXPORTS = [
     "lbm_set_closure_weights", "lbm_state_bytes", "lbm_get_state", "lbm_set_state",
     "lbm_strerror", "lbm_last_error", "lbm_copy_probe", "lbm_pattern_probe",
     "lbm_mlp_create", "lbm_mlp_destroy", "lbm_mlp_set_params", "lbm_mlp_get_params",
-    "lbm_mlp_forward", "lbm_mlp_loss_grad", "lbm_mlp_adam_step", "lbm_mlp_take_loss",
+    "lbm_mlp_forward", "lbm_mlp_loss_grad", "lbm_mlp_loss_grad_noalloc", "lbm_mlp_adam_step", "lbm_mlp_take_loss",
     "lbm_mlp_last_error", "lbm_set_turbine", "lbm_turbine_loads", "lbm_turbine_points", "lbm_turbine_box",
 ]
 
@@ -137,6 +137,7 @@ def lib():
         "lbm_mlp_get_params": [vp, fp, sz],
         "lbm_mlp_forward": [vp, vp, sz, vp],
         "lbm_mlp_loss_grad": [vp, vp, vp, sz, fp],
+        "lbm_mlp_loss_grad_noalloc": [vp, vp, vp, sz, fp],
         "lbm_mlp_adam_step": [vp, C.c_float, C.c_float, C.c_float, C.c_float],
         "lbm_mlp_take_loss": [vp, _D],
     }
@@ -510,6 +511,16 @@ class MlpTrainer:
         gp = g.ctypes.data_as(C.POINTER(C.c_float)) if want_grad else None
         self._check(lib().lbm_mlp_loss_grad(self._h, C.c_void_p(feat.data_ptr()),
                                             C.c_void_p(target.data_ptr()), feat.shape[0], gp))
+        return g
+
+    def loss_grad_noalloc(self, feat, target, want_grad=False):
+        """lbm_mlp_loss_grad_noalloc: the same result through the library's
+        static scratch (no device allocation; at most 65536 samples)."""
+        self._sync_inputs(feat, target)
+        g = np.empty(1313, dtype=np.float32) if want_grad else None
+        gp = g.ctypes.data_as(C.POINTER(C.c_float)) if want_grad else None
+        self._check(lib().lbm_mlp_loss_grad_noalloc(self._h, C.c_void_p(feat.data_ptr()),
+                                                    C.c_void_p(target.data_ptr()), feat.shape[0], gp))
         return g
 
     def adam_step(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
