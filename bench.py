@@ -134,6 +134,18 @@ def measured_traffic():
     return {k: float(v) for k, v in vals.items() if k != "source_sha256_16"}
 
 
+def cpu_model():
+    """The host CPU's model name (first entry of /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(sample_n=128, steps=100):
     """The FP64 oracle on the host cores, on a bounded sample of the same
     recipe (a sample_n^3 periodic box, same spectrum and omega)."""
@@ -148,7 +160,7 @@ def cpu_baseline(sample_n=128, steps=100):
     dt = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": sample_n ** 3 * steps / dt / 1e6, "unit": "MLUPS", "cores": cores,
-            "kind": "oracle",
+            "cpu_model": cpu_model(), "kind": "oracle",
             "sample": f"{sample_n}^3 periodic box of the same random-phase recipe, {steps} steps, "
                       f"FP64 two-array oracle ({dt:.1f} s)"}
 

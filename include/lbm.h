@@ -83,7 +83,17 @@ typedef struct {
                               inflow/outflow rules where offsets fit); 1: the
                               64-bit general boundary path on every cell, for
                               validation. Results agree to rounding. */
+    int rounding;          /* 16-bit storage: how the stepping kernels round
+                              the stored deviations. LBM_ROUND_STOCHASTIC
+                              (0, default): to one of the two neighbouring
+                              representable values with probability by
+                              distance (expected value exact), so that a
+                              steady flow does not accumulate the same
+                              rounding step after step; LBM_ROUND_NEAREST
+                              (1): to nearest even. Initialisation rounds to
+                              nearest either way. No effect on FP32. */
 } lbm_config;
+typedef enum { LBM_ROUND_STOCHASTIC = 0, LBM_ROUND_NEAREST = 1 } lbm_rounding;
 
 /* Create a context (validates cfg; no device memory is touched yet). */
 int lbm_create(const lbm_config *cfg, lbm_ctx **out);

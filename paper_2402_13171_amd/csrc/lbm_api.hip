@@ -295,6 +295,7 @@ int lbm_create(const lbm_config *cfg, lbm_ctx **out) {
             if (b != LBM_BC_PERIODIC && b != LBM_BC_NOSLIP && b != LBM_BC_FREESLIP) return LBM_EINVAL;
         if ((c.bc_z_lo == LBM_BC_PERIODIC) != (c.bc_z_hi == LBM_BC_PERIODIC)) return LBM_EINVAL;
         if (c.check_every < 0) return LBM_EINVAL;
+        if (c.rounding != LBM_ROUND_STOCHASTIC && c.rounding != LBM_ROUND_NEAREST) return LBM_EINVAL;
 
         lbm_ctx *x = new (std::nothrow) lbm_ctx();
         if (!x) return LBM_ENOMEM;
@@ -1039,15 +1040,18 @@ int lbm_step(lbm_ctx *c, int nsteps) {
         const int nrot = (int)c->h_rots.size();
         for (int s = 0; s < nsteps; ++s) {
             Physics ph = physics_of(c);
+            ph.sr_seed = mix32((uint32_t)c->t * SR_WEYL + 0x632be5abu);
             const bool frc = has_force(c);
             if (c->d_in_mean &&
                 launch_inflow(uin_plane(c, c->t), c->d_in_mean, c->d_in_box, c->in_lt > 0 ? c->in_lt : 1,
                               c->cfg.ny * c->cfg.nz, c->in_advect * (double)c->t, c->stream))
                 return fail(c, LBM_EHIP, "inflow launch failed");
             g = geo_of(c);
+            const int sr = c->cfg.rounding == LBM_ROUND_STOCHASTIC;
             if (nrot > 0 && launch_alm(st, c->parity, g, ph, c->h_rots.data(), c->d_rots, nrot, c->t, c->stream))
                 return fail(c, LBM_EHIP, "actuator-line launch failed");
-            if (launch_stream_collide(st, c->parity, (int)c->cfg.closure, mode, frc, c->general_rates, g, ph, c->stream))
+            if (launch_stream_collide(st, sr, c->parity, (int)c->cfg.closure, mode, frc, c->general_rates, g, ph,
+                                      c->stream))
                 return fail(c, LBM_EHIP, "stream-collide launch failed");
             c->parity ^= 1;
             c->t += 1;

@@ -10,6 +10,8 @@
 #include <hip/hip_fp16.h>
 #include <stdint.h>
 
+#include "lbm_internal.h"
+
 namespace lbm {
 
 // ------------------------------------------------------------ lattice
@@ -48,6 +50,74 @@ template <> struct Store<bf16_t> {
     static __device__ __forceinline__ float ld(const bf16_t *p) { return bf16_bits_to_f32(p->v); }
     static __device__ __forceinline__ void st(bf16_t *p, float v) { p->v = f32_to_bf16_bits(v); }
 };
+// The same two storage formats as written by the stepping kernels with
+// stochastic rounding (the values reach the store already on the grid, see
+// sr_round_cell; the conversion there is exact).
+struct f16_sr { uint16_t v; };
+struct bf16_sr { uint16_t v; };
+template <> struct Store<f16_sr> {
+    static __device__ __forceinline__ float ld(const f16_sr *p) { return Store<__half>::ld((const __half *)p); }
+    static __device__ __forceinline__ void st(f16_sr *p, float v) { Store<__half>::st((__half *)p, v); }
+};
+template <> struct Store<bf16_sr> {
+    static __device__ __forceinline__ float ld(const bf16_sr *p) { return Store<bf16_t>::ld((const bf16_t *)p); }
+    static __device__ __forceinline__ void st(bf16_sr *p, float v) { Store<bf16_t>::st((bf16_t *)p, v); }
+};
+
+// ------------------------------------------------------------ stochastic rounding
+// With LBM_ROUND_STOCHASTIC (storage types f16_sr / bf16_sr below), the
+// 16-bit stores of the stepping kernels round stochastically: a value between
+// two representable neighbours goes to the upper one with probability equal
+// to its distance from the lower one over their spacing, using gfx950's
+// conversion instructions with a random operand (v_cvt_sr_f16_f32,
+// v_cvt_sr_bf16_f32). The expected stored value is then the value itself, so
+// the rounding of a steady flow does not add up to a drift step after step
+// (round-to-nearest rounds a steady value the same way every step); the
+// error becomes a zero-mean perturbation that the viscosity damps. Values
+// already representable (the rest state, for one) are stored exactly.
+// Random words: mix32 (lbm_internal.h) of the cell index and a per-step
+// seed, plus a Weyl increment per direction; deterministic for a given cell,
+// step and direction.
+
+typedef _Float16 f16x2_native __attribute__((ext_vector_type(2)));
+// Two values rounded stochastically to the storage type's grid, returned as
+// floats (exact in the storage type, so the store's own conversion keeps
+// them unchanged); the two conversions fill the halves of one register.
+template <typename T> struct SrRound {
+    static __device__ __forceinline__ void q2(float &a, float &b, uint32_t, uint32_t) {}
+};
+template <> struct SrRound<f16_sr> {
+    static __device__ __forceinline__ void q2(float &a, float &b, uint32_t ra, uint32_t rb) {
+        f16x2_native z = __builtin_amdgcn_cvt_sr_f16_f32(__builtin_bit_cast(f16x2_native, a), a, ra, false);
+        z = __builtin_amdgcn_cvt_sr_f16_f32(z, b, rb, true);
+        a = (float)z[0];
+        b = (float)z[1];
+    }
+};
+template <> struct SrRound<bf16_sr> {
+    static __device__ __forceinline__ void q2(float &a, float &b, uint32_t ra, uint32_t rb) {
+        bf16x2_native z = __builtin_amdgcn_cvt_sr_bf16_f32(__builtin_bit_cast(bf16x2_native, a), a, ra, false);
+        z = __builtin_amdgcn_cvt_sr_bf16_f32(z, b, rb, true);
+        a = (float)z[0];
+        b = (float)z[1];
+    }
+};
+// the 27 post-collision values of one cell
+template <typename T> inline constexpr bool rounds_stochastically = false;
+template <> inline constexpr bool rounds_stochastically<f16_sr> = true;
+template <> inline constexpr bool rounds_stochastically<bf16_sr> = true;
+template <typename T>
+__device__ __forceinline__ void sr_round_cell(float *o, uint32_t cell, uint32_t seed) {
+    if constexpr (rounds_stochastically<T>) {
+        const uint32_t h = mix32(cell ^ seed);
+        float spare = 0.0f;
+#pragma unroll
+        for (int i = 0; i < 27; i += 2) {
+            float &b = i + 1 < 27 ? o[i + 1] : spare;
+            SrRound<T>::q2(o[i], b, h + (uint32_t)i * SR_WEYL, h + (uint32_t)(i + 1) * SR_WEYL);
+        }
+    }
+}
 
 // ------------------------------------------------------------ collision
 // Closure kinds (values match lbm_closure).

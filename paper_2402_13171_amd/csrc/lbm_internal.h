@@ -12,6 +12,19 @@ constexpr int MLP_NBLOB = 1326;
 
 enum Bc { BC_PERIODIC = 0, BC_INOUT = 1, BC_NOSLIP = 2, BC_FREESLIP = 3 };
 
+// 32-bit finaliser of MurmurHash3 (Appleby): the random words of the
+// stochastic rounding of 16-bit stores (per-step seed on the host, per cell
+// on the device) and SR_WEYL, the golden-ratio Weyl increment between them.
+__host__ __device__ __forceinline__ uint32_t mix32(uint32_t h) {
+    h ^= h >> 16;
+    h *= 0x85ebca6bu;
+    h ^= h >> 13;
+    h *= 0xc2b2ae35u;
+    h ^= h >> 16;
+    return h;
+}
+constexpr uint32_t SR_WEYL = 0x9e3779b9u;
+
 // Force box of one rotor: [3][bnx*bny*bnz] FP32, x fastest.
 struct ForceBox {
     int x0, y0, z0, bnx, bny, bnz;
@@ -49,6 +62,7 @@ struct Geo {
     int skip_zlo, skip_zhi;
 };
 
+
 struct Physics {
     float omega, omega2, tau0, smag_c;  // smag_c = 18 sqrt(2) Cs^2
     float nu0;
@@ -58,6 +72,7 @@ struct Physics {
     int nbox;
     ForceBox box[MAX_ROTORS];
     const MlpDev *mlp;
+    uint32_t sr_seed;                   // stochastic rounding of 16-bit stores: per-step seed
 };
 
 // Turbine topology tree (Sec. 3.3): one node as the point kernel reads it.
@@ -115,7 +130,8 @@ constexpr int PT_STRIDE = 10;
 // steps and on all cells off the z walls in odd steps, whose wall planes take
 // the general path)
 enum { SC_FAST = 0, SC_GENERAL = 1, SC_SPLIT = 2 };
-int launch_stream_collide(int storage, int parity, int closure, int mode, bool force,
+// stochastic != 0: 16-bit stores round stochastically (lbm_config.rounding)
+int launch_stream_collide(int storage, int stochastic, int parity, int closure, int mode, bool force,
                           bool general_rates, const Geo &g, const Physics &ph, hipStream_t s);
 int launch_init_tgv(int storage, const Geo &g, double u0, double k, double rho0, hipStream_t s);
 int launch_pattern_probe(int storage, int parity, const Geo &g, hipStream_t s);

@@ -247,6 +247,7 @@ __device__ __forceinline__ void cell_update(const Geo &g, const Physics &ph, int
     if (GR) collide_general(d, m, om1, ph.omega2, ph.omega_hi, Fx, Fy, Fz, o);
     else collide_unit_rates(m, om1, ph.omega2, Fx, Fy, Fz, o);
     if (CL == CL_MLP && !valid) return;
+    sr_round_cell<T>(o, (uint32_t)cell, ph.sr_seed);
     // the closure variant needs scalar registers for the network: an opaque
     // copy of the plane stride makes the compiler rebuild the plane bases of
     // the stores here instead of holding them from the loads on
@@ -489,14 +490,17 @@ static int launch_sc_par(int parity, int closure, int mode, bool frc, bool gr, c
                        : launch_sc_cl<T, 1>(closure, mode, frc, gr, g, ph, s);
 }
 
-int launch_stream_collide(int storage, int parity, int closure, int mode, bool force, bool general_rates,
-                          const Geo &g, const Physics &ph, hipStream_t s) {
+int launch_stream_collide(int storage, int stochastic, int parity, int closure, int mode, bool force,
+                          bool general_rates, const Geo &g, const Physics &ph, hipStream_t s) {
     if (mode != SC_FAST && mode != SC_GENERAL && mode != SC_SPLIT) return -1;
     int rc;
-    switch (storage) {
-        case 0: rc = launch_sc_par<float>(parity, closure, mode, force, general_rates, g, ph, s); break;
-        case 1: rc = launch_sc_par<__half>(parity, closure, mode, force, general_rates, g, ph, s); break;
-        case 2: rc = launch_sc_par<bf16_t>(parity, closure, mode, force, general_rates, g, ph, s); break;
+    switch (storage * 2 + (stochastic ? 1 : 0)) {
+        case 0:
+        case 1: rc = launch_sc_par<float>(parity, closure, mode, force, general_rates, g, ph, s); break;
+        case 2: rc = launch_sc_par<__half>(parity, closure, mode, force, general_rates, g, ph, s); break;
+        case 3: rc = launch_sc_par<f16_sr>(parity, closure, mode, force, general_rates, g, ph, s); break;
+        case 4: rc = launch_sc_par<bf16_t>(parity, closure, mode, force, general_rates, g, ph, s); break;
+        case 5: rc = launch_sc_par<bf16_sr>(parity, closure, mode, force, general_rates, g, ph, s); break;
         default: return -1;
     }
     if (rc) return rc;

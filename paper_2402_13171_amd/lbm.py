@@ -44,7 +44,8 @@ class Config(C.Structure):
                 ("storage", C.c_int), ("closure", C.c_int), ("cs_smag", C.c_double),
                 ("bc_x", C.c_int), ("bc_z_lo", C.c_int), ("bc_z_hi", C.c_int),
                 ("u_in", C.c_double * 3), ("body_force", C.c_double * 3),
-                ("check_every", C.c_int), ("stream", C.c_void_p), ("general_path", C.c_int)]
+                ("check_every", C.c_int), ("stream", C.c_void_p), ("general_path", C.c_int),
+                ("rounding", C.c_int)]
 
 
 _D = C.POINTER(C.c_double)
@@ -61,6 +62,7 @@ class Rotor(C.Structure):
 
 
 KERNELS = {"gauss": 0, "roma3": 1}
+ROUNDING = {"stochastic": 0, "nearest": 1}
 
 
 class Node(C.Structure):
@@ -230,7 +232,8 @@ class Lbm:
 
     def __init__(self, nx, ny, nz, omega=1.9, omega_hi=None, storage="f32", closure="none",
                  cs_smag=0.1, bc_x="periodic", bc_z=("periodic", "periodic"), u_in=(0, 0, 0),
-                 body_force=(0, 0, 0), check_every=0, general_path=False, device="cuda:0"):
+                 body_force=(0, 0, 0), check_every=0, general_path=False, rounding="stochastic",
+                 device="cuda:0"):
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -251,6 +254,7 @@ class Lbm:
         cfg.check_every = check_every
         cfg.stream = self.stream.cuda_stream
         cfg.general_path = int(bool(general_path))
+        cfg.rounding = ROUNDING[rounding]
         self.cfg = cfg
         self.shape = (nz, ny, nx)
         self.n = nx * ny * nz

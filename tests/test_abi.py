@@ -36,7 +36,8 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_sizes_match_header_layout():
     from paper_2402_13171_amd import lbm
-    # lbm_config: 3 ints, pad, 10 doubles, 2 ints, double, 3 ints, pad, 6 doubles, int, pad, pointer
+    # lbm_config: 3 ints, pad, 10 doubles, 2 ints, double, 3 ints, pad, 6 doubles, int, pad, pointer,
+    # 2 ints (general_path, rounding)
     assert ctypes.sizeof(lbm.Config) == 3 * 4 + 4 + 10 * 8 + 2 * 4 + 8 + 3 * 4 + 4 + 6 * 8 + 4 + 4 + 8 + 8
     assert ctypes.sizeof(lbm.Rotor) == 6 * 8 + 5 * 8 + 2 * 4 + 4 * 8 + 8 + 3 * 8 + 2 * 4
     # lbm_node: 6 ints, 31 doubles (pos, rot, axis, 5 motion values, disp, dir, normal, coef, pitch), 4 pointers

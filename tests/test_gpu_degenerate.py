@@ -59,7 +59,9 @@ def test_rest_state_is_preserved(storage, case):
     exactly 0 through both AA parities (the collision maps zero to zero). A
     resting inlet feeds phi(0)^3 - w evaluated in FP32, which is zero only up
     to rounding (a few 1e-10 here), so the open box stays at rest to that
-    level through the inflow/outflow and wall rules."""
+    level through the inflow/outflow and wall rules. FP16 storage rounds
+    stochastically: a residue of 1e-11 is stored as 0 or, rarely, as the
+    smallest FP16 step 2^-24 (6e-8), so there the bound is that step."""
     _need_gpu()
     from paper_2402_13171_amd.lbm import Lbm
     nx, ny, nz = 37, 9, 6
@@ -73,8 +75,9 @@ def test_rest_state_is_preserved(storage, case):
         assert not np.any(u)
         assert np.abs(rho - 1.0).max() <= 1e-15  # FP64 sum of the 27 weights
     else:
-        assert np.abs(sim.pops() - w).max() <= 1e-8
-        assert np.abs(u).max() <= 1e-8 and np.abs(rho - 1.0).max() <= 1e-8
+        tol = 2.0 ** -24 if storage == "f16" else 1e-8
+        assert np.abs(sim.pops() - w).max() <= tol
+        assert np.abs(u).max() <= 27 * tol and np.abs(rho - 1.0).max() <= 27 * tol
 
 
 def test_zero_steps_and_empty_sample():

@@ -101,15 +101,13 @@ def test_floating_turbine_tree_over_2000_steps():
 def test_closure_row_analogue_over_1000_steps():
     """The reduced turbine-row case (96 x 32 x 32, ground wall, free-slip top,
     sheared inflow with a convected turbulence box, one rotor) with the learned
-    closure, 1000 steps, FP32 and FP16 storage side by side against one FP64
-    oracle run (bfloat16-emulating closure mode). FP32 storage stays within
-    the 1e-5 bar: the path is exact up to FP32 rounding over the whole run.
-    FP16 storage is reported along the run; its gate, 2e-2 at 1000 steps, is
-    the random walk of its per-step rounding (about 8e-5 of the largest
-    speed per step and cell, sqrt(1000) steps, about 4.4 standard deviations
-    for the largest of 10^5 cells: 1.1e-2), doubled. In this sheared,
-    wall-bounded inflow the 1e-3 bar of 16-bit storage is passed after about
-    50 steps."""
+    closure, 1000 steps, against one FP64 oracle run (bfloat16-emulating
+    closure mode): FP32 storage within 1e-5 (the path is exact up to FP32
+    rounding over the whole run); FP16 storage with the default stochastic
+    rounding within the 1e-3 bar of 16-bit storage at every checkpoint; FP16
+    with round-to-nearest reported beside it (in this near-steady inflow it
+    rounds the same values the same way step after step and drifts past
+    1e-3 after about 50 steps)."""
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no HIP device")
@@ -129,29 +127,33 @@ def test_closure_row_analogue_over_1000_steps():
     ref.init_fields(rho0, u0)
     ref.set_rotor(0, rot)
     sims = {}
-    for storage in ("f32", "f16"):
-        sim = Lbm(nx, ny, nz, omega=1.9, storage=storage, closure="mlp", bc_x="inout", bc_z=("noslip", "freeslip"))
+    for name, storage, rounding in (("f32", "f32", "stochastic"), ("f16", "f16", "stochastic"),
+                                    ("f16-nearest", "f16", "nearest")):
+        sim = Lbm(nx, ny, nz, omega=1.9, storage=storage, closure="mlp", bc_x="inout", bc_z=("noslip", "freeslip"),
+                  rounding=rounding)
         sim.set_closure_weights(blob)
         sim.init_fields(rho0, u0)
         sim.set_inflow(mean, box, advect=0.05)
         sim.set_rotor(0, rot)
-        sims[storage] = sim
-    err = {}
+        sims[name] = sim
+    worst = {k: 0.0 for k in sims}
     for t in range(1000):
         ref.set_inlet_plane(oracle.inflow_plane(mean, box, 0.05, t))
         ref.step(1)
         for sim in sims.values():
             sim.step(1)
-        if (t + 1) in (10, 50, 100, 250, 500, 1000):
+        if (t + 1) in (10, 50, 100, 250, 500, 750, 1000):
             _, ur = ref.fields()
             den = np.linalg.norm(ur, axis=0).max()
-            for storage, sim in sims.items():
+            err = {}
+            for name, sim in sims.items():
                 _, ug = sim.fields()
-                err[storage] = np.linalg.norm(ug - ur, axis=0).max() / den
+                err[name] = np.linalg.norm(ug - ur, axis=0).max() / den
+                worst[name] = max(worst[name], err[name])
             print(f"closure row analogue, step {t + 1}: velocity eps_max FP32 {err['f32']:.2e}, "
-                  f"FP16 {err['f16']:.2e}", flush=True)
-    assert err["f32"] <= 1e-5
-    assert err["f16"] <= 2e-2
+                  f"FP16 stochastic {err['f16']:.2e}, FP16 nearest {err['f16-nearest']:.2e}", flush=True)
+    assert worst["f32"] <= 1e-5
+    assert worst["f16"] <= 1e-3
 
 
 @opt_in

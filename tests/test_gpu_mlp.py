@@ -65,6 +65,13 @@ def test_gradient_matches_emulated_oracle():
     _, gexact = mlp_ref.loss_and_grad(blob, feats.astype(np.float64), tgt.astype(np.float64))
     rel_exact = np.linalg.norm(g - gexact) / np.linalg.norm(gexact)
     print(f"mlp gradient: rel norm error {rel:.2e} (emulated), {rel_exact:.2e} (exact FP64)")
+    # The network is specified with bfloat16 weights and activations on the
+    # matrix cores: the oracle of that arithmetic is the FP64 oracle with the
+    # same operands rounded to bfloat16, held to 1e-4 here (the 1e-3 bar on
+    # gradients with a margin). Against the network with unrounded FP64
+    # operands the difference is the bfloat16 rounding itself: 2^-9 relative
+    # per operand through products of several rounded factors, about 1e-2 in
+    # norm; that gate only checks the size of the effect.
     assert rel <= 1e-4
     assert rel_exact <= 3e-2
     assert tr.take_loss() == pytest.approx(L, rel=1e-5)
@@ -89,7 +96,8 @@ def test_adam_step_matches_oracle():
 
 
 def test_training_reduces_loss():
-    """Fit a teacher network's output: the loss falls by a large factor."""
+    """Fit a teacher network's output: the loss of the trained student falls
+    below a tenth of the untrained student's loss on the same samples."""
     _need_gpu()
     import torch
     from paper_2402_13171_amd.lbm import MlpTrainer
@@ -103,16 +111,20 @@ def test_training_reduces_loss():
     tr = MlpTrainer(student)
     F = torch.from_numpy(feats).cuda()
     Y = torch.from_numpy(y).cuda()
+    for b in range(0, m, 4096):  # loss of the untrained student (no update)
+        tr.loss_grad(F[b:b + 4096], Y[b:b + 4096])
+    loss0 = tr.take_loss()
     losses = []
-    for epoch in range(30):
+    for epoch in range(40):
         perm = torch.randperm(m, device="cuda", generator=torch.Generator(device="cuda").manual_seed(epoch))
         Fp, Yp = F[perm].contiguous(), Y[perm].contiguous()
         for b in range(0, m, 4096):
             tr.loss_grad(Fp[b:b + 4096], Yp[b:b + 4096])
             tr.adam_step(lr=3e-3)
         losses.append(tr.take_loss())
-    print("training loss per epoch:", " ".join(f"{v:.3e}" for v in losses[::5]))
-    assert losses[-1] < losses[0] / 5
+    print(f"untrained loss {loss0:.3e}; training loss per epoch:", " ".join(f"{v:.3e}" for v in losses[::5]),
+          f"last {losses[-1]:.3e}")
+    assert losses[-1] < loss0 / 10
 
 
 def test_fused_closure_in_lattice_matches_oracle():
