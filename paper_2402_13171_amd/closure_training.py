@@ -94,17 +94,19 @@ def shell_spectrum(u):
     return workloads.shell_spectrum(u)
 
 
-def fine_run(n_fine, seed, omega, w, snap_steps, log=print, storage="f32"):
-    """Fine run; returns {step: filtered [10, n/w...]} for the requested steps."""
+def fine_run(n_fine, seed, omega, widths, snap_steps, log=print, storage="f32"):
+    """Fine run; returns {w: {step: filtered [10, n/w...]}} for the requested
+    filter widths and steps (one run serves every width)."""
     sim = Lbm(n_fine, n_fine, n_fine, omega=omega, storage=storage)
     rho, u = workloads.random_phase_field(n_fine, seed=seed)
     sim.init_fields(rho, u)
     del rho, u
-    out = {}
+    out = {w: {} for w in widths}
     for s in sorted(snap_steps):
         sim.step(s - sim.time)
-        out[s] = sim.filtered(w)
-        log(f"fine run seed {seed}: step {s} filtered")
+        for w in widths:
+            out[w][s] = sim.filtered(w)
+        log(f"fine run seed {seed}: step {s} filtered ({', '.join(str(w) for w in widths)})")
     sim.close()
     return out
 
@@ -121,7 +123,7 @@ def train(feats, targets, blob0, epochs=8, batch=4096, lr=2e-3, seed=0, log=prin
     for e in range(epochs):
         perm = torch.randperm(m, device="cuda", generator=gen)
         Fp, Yp = F[perm].contiguous(), Y[perm].contiguous()
-        lr_e = lr * (0.5 ** (e // 3))
+        lr_e = lr * (0.5 ** (e // 5))
         for b in range(0, m - batch + 1, batch):
             tr.loss_grad(Fp[b:b + batch], Yp[b:b + batch])
             tr.adam_step(lr=lr_e)

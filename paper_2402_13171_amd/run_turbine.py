@@ -18,8 +18,9 @@ on a pitching and surging platform), vawt (vertical-axis rotor, D = 32, with
 its shaft) or disk (actuator disk, D = 32, C_T' = 4/3). Reports MLUPS with
 and without it and per-component loads over the last rotor revolution.
 
-row: 1024 x 256 x 256, FP16 storage, learned closure, three rotors of
-diameter 48 spaced 5 D apart, ground wall (bounce-back) and free-slip top,
+row: 1024 x 256 x 256, FP16 storage (--storage f32 for the FP32 comparison
+run), learned closure, three rotors of diameter 48 spaced 5 D apart, ground
+wall (bounce-back) and free-slip top,
 sheared inflow u = 0.05 ((z + 1/2)/128)^0.14 plus a convected frozen
 turbulence box (5 % intensity), 5000 steps; per-rotor thrust and power.
 """
@@ -166,7 +167,7 @@ def row(args, log):
     mean, box = workloads.turbine_row_inflow(ny=ny, nz=nz)
     blob = np.load(args.weights).astype(np.float64) if args.weights else None
     closure = "mlp" if blob is not None else "smag"
-    sim = Lbm(nx, ny, nz, omega=args.omega, storage="f16", closure=closure, cs_smag=0.1, bc_x="inout",
+    sim = Lbm(nx, ny, nz, omega=args.omega, storage=args.storage, closure=closure, cs_smag=0.1, bc_x="inout",
               bc_z=("noslip", "freeslip"), check_every=500)
     if blob is not None:
         sim.set_closure_weights(blob)
@@ -189,7 +190,10 @@ def row(args, log):
     last = s[s[:, 0] > s[-1, 0] - 2 * per_rev]
     n = nx * ny * nz
     out = {
-        "workload": "turbine row 1024x256x256 FP16 + " + closure + " closure, 3 rotors D=48, sheared turbulent inflow",
+        "workload": f"turbine row 1024x256x256 {args.storage.upper()} + " + closure
+                    + " closure, 3 rotors D=48, sheared turbulent inflow",
+        "storage": args.storage, "rounding": "stochastic" if args.storage != "f32" else None,
+        "weights": args.weights,
         "steps": sim.time, "mlups": n / (np.median(ms) * 1e-3) / 1e6,
         "per_rotor_mean_last_two_revolutions": [
             {"thrust": float(last[:, 1 + 3 * k].mean()), "torque": float(last[:, 2 + 3 * k].mean()),
@@ -211,6 +215,7 @@ def main(argv=None):
     ap.add_argument("--kernel", choices=["gauss", "roma3"], default="gauss",
                     help="force spreading kernel (single case)")
     ap.add_argument("--tip-loss", action="store_true", help="Prandtl tip-loss factor (single case)")
+    ap.add_argument("--storage", choices=["f16", "bf16", "f32"], default="f16", help="population storage (row case)")
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
     if a.steps is None:
@@ -219,7 +224,8 @@ def main(argv=None):
     log = lambda *m: print(f"[{time.time() - t_start:7.1f}s]", *m, flush=True)
     res = {"single": single, "row": row, "tree": tree}[a.case](a, log)
     default = {"single": f"results/single_turbine_{a.kernel}{'_tiploss' if a.tip_loss else ''}.json",
-               "row": "results/turbine_row.json", "tree": f"results/tree_{a.config}.json"}
+               "row": f"results/turbine_row{'' if a.storage == 'f16' else '_' + a.storage}.json",
+               "tree": f"results/tree_{a.config}.json"}
     out = a.out or default[a.case]
     os.makedirs(os.path.dirname(out) or ".", exist_ok=True)
     with open(out, "w") as fh:
