@@ -291,31 +291,16 @@ __global__ __launch_bounds__(ALM_BLOCK) void k_alm_points(Geo g, Physics ph, Rot
                     o[9 + a] = m[a];
                 }
             }
-            // Gaussian normalisation over the 13 nodes per axis (separable);
-            // the Roma delta sums to one as it stands
-            int c0[3];
-            double S = 1.0;
-            for (int ax = 0; ax < 3; ++ax) {
-                c0[ax] = (int)floor(xp[ax] + 0.5);
-                if (R.kernel == LBM_KERNEL_GAUSS) {
-                    // FP32 terms, the precision of the spread weights themselves
-                    const float ie2 = (float)(1.0 / (R.eps * R.eps)), e0 = (float)(c0[ax] - xp[ax]);
-                    float sa = 0.0f;
-                    for (int d = -SUPPORT; d <= SUPPORT; ++d) {
-                        const float e = e0 + (float)d;
-                        sa += expf(-e * e * ie2);
-                    }
-                    S *= (double)sa;
-                }
-            }
+            // the record the spreading kernel reads (which also normalises the
+            // Gaussian weights, from the per-axis tables it builds anyway)
             float *Pt = R.pts + (size_t)p * PT_STRIDE;
             for (int ax = 0; ax < 3; ++ax) {
-                Pt[ax] = (float)(xp[ax] - c0[ax]);  // offset from the nearest node
+                const int c0 = (int)floor(xp[ax] + 0.5);
+                Pt[ax] = (float)(xp[ax] - c0);  // offset from the nearest node
                 Pt[3 + ax] = (float)(-Fp[ax]);
-                Pt[6 + ax] = (float)c0[ax];
+                Pt[6 + ax] = (float)c0;
                 if (!R.nodes) R.pt_force[3 * p + ax] = Fp[ax];
             }
-            Pt[9] = (float)(1.0 / S);
         }
         s_red[threadIdx.x][0] = accT;
         s_red[threadIdx.x][1] = accQ;
@@ -338,12 +323,20 @@ __global__ __launch_bounds__(ALM_BLOCK) void k_alm_points(Geo g, Physics ph, Rot
 // Gather-form spreading over one slot's box: F(X) = sum_p (-F_p) eta(X - x_p) / W_p.
 // One workgroup per tile of SP_TX x SP_TY x SP_TZ box cells. The workgroup
 // first keeps, in point order, the points whose support reaches the tile
-// (a ballot compaction per wave, then the waves' counts in order), stages
-// them in LDS, and each cell then sums over those points only: the same
+// (a ballot compaction per wave, then the waves' counts in order). Both
+// kernels are products of one factor per axis (the Gaussian's exponential
+// splits, Roma's delta is defined that way), so the workgroup tabulates, for
+// each kept point, the factor of every support offset on each axis in LDS
+// (Gaussian: W_p, the sum of its weights over the support, is the product of
+// the three table sums; the Roma delta's weights sum to one), and each cell
+// then sums over the kept points with three table reads per point: the same
 // terms in the same order as a sum over every point that skips the ones out
-// of reach, so the result does not depend on the tiling.
+// of reach, so the result does not depend on the tiling. Points are taken
+// in chunks of SP_CHUNK.
 constexpr int SP_TX = 16, SP_TY = 4, SP_TZ = 4;
 static_assert(SP_TX * SP_TY * SP_TZ == ALM_BLOCK, "one cell per thread");
+constexpr int SP_CHUNK = 64;
+constexpr int SP_W = 2 * SUPPORT + 1;  // widest support (Gaussian), offsets -SUPPORT..SUPPORT
 
 // One launch spreads every slot: workgroups [first[r], first[r+1]) take the
 // tiles of slot r (tile counts per axis in tiles[r]).
@@ -360,10 +353,12 @@ __global__ __launch_bounds__(ALM_BLOCK) void k_alm_spread(const RotorDev *rots, 
     const RotorDev &R = rots[rid];
     const int npts = R.npts;
     const ForceBox &B = R.box;
-    const int half = R.half;
-    __shared__ float sp[ALM_MAX_PTS * PT_STRIDE];
+    const int half = R.half, W = 2 * half + 1;  // half <= SUPPORT (checked on the host)
     __shared__ int s_idx[ALM_MAX_PTS];
     __shared__ int s_wave[ALM_BLOCK / 64];
+    __shared__ float s_g[SP_CHUNK][3][SP_W];  // per-axis factors of the kept points
+    __shared__ float s_f[SP_CHUNK][4];        // -F_p and 1 / W_p
+    __shared__ int s_c[SP_CHUNK][3];          // nearest node of the point
     const int tx = blk % tiles_x, ty = (blk / tiles_x) % tiles_y, tz = blk / (tiles_x * tiles_y);
     // tile extent in lattice coordinates (clipped to the box)
     const int X0 = B.x0 + tx * SP_TX, Y0 = B.y0 + ty * SP_TY, Z0 = B.z0 + tz * SP_TZ;
@@ -389,26 +384,55 @@ __global__ __launch_bounds__(ALM_BLOCK) void k_alm_spread(const RotorDev *rots, 
         for (int w = 0; w < ALM_BLOCK / 64; ++w) count += s_wave[w];
         __syncthreads();
     }
-    for (int q = threadIdx.x; q < count * PT_STRIDE; q += ALM_BLOCK)
-        sp[q] = R.pts[(size_t)s_idx[q / PT_STRIDE] * PT_STRIDE + q % PT_STRIDE];
-    __syncthreads();
     const int X = X0 + (int)(threadIdx.x % SP_TX), Y = Y0 + (int)((threadIdx.x / SP_TX) % SP_TY),
               Z = Z0 + (int)(threadIdx.x / (SP_TX * SP_TY));
-    if (X > X1 || Y > Y1 || Z > Z1) return;
+    const bool mine = X <= X1 && Y <= Y1 && Z <= Z1;  // threads past the box edge keep to the barriers
     const float ie2 = R.kernel == LBM_KERNEL_GAUSS ? (float)(1.0 / (R.eps * R.eps)) : 0.0f;
     const bool roma = R.kernel == LBM_KERNEL_ROMA3;  // uniform over the grid
     float Fx = 0.f, Fy = 0.f, Fz = 0.f;
-    for (int k = 0; k < count; ++k) {
-        const float *P = sp + k * PT_STRIDE;
-        const int dx = X - (int)P[6], dy = Y - (int)P[7], dz = Z - (int)P[8];
-        if (abs(dx) > half || abs(dy) > half || abs(dz) > half) continue;
-        const float ex = (float)dx - P[0], ey = (float)dy - P[1], ez = (float)dz - P[2];
-        const float w = roma ? roma_phi(ex) * roma_phi(ey) * roma_phi(ez)
-                             : expf(-(ex * ex + ey * ey + ez * ez) * ie2) * P[9];
-        Fx = fmaf(w, P[3], Fx);
-        Fy = fmaf(w, P[4], Fy);
-        Fz = fmaf(w, P[5], Fz);
+    for (int c0 = 0; c0 < count; c0 += SP_CHUNK) {
+        const int nk = min(SP_CHUNK, count - c0);
+        // factors: e = d - (x_p - node) for d = -half..half on each axis
+        for (int q = threadIdx.x; q < nk * 3 * W; q += ALM_BLOCK) {
+            const int k = q / (3 * W), ax = (q / W) % 3, d = q % W - half;
+            const float e = (float)d - R.pts[(size_t)s_idx[c0 + k] * PT_STRIDE + ax];
+            s_g[k][ax][d + half] = roma ? roma_phi(e) : expf(-e * e * ie2);
+        }
+        for (int q = threadIdx.x; q < nk; q += ALM_BLOCK) {
+            const float *P = R.pts + (size_t)s_idx[c0 + q] * PT_STRIDE;
+            s_f[q][0] = P[3];
+            s_f[q][1] = P[4];
+            s_f[q][2] = P[5];
+            s_c[q][0] = (int)P[6];
+            s_c[q][1] = (int)P[7];
+            s_c[q][2] = (int)P[8];
+        }
+        __syncthreads();
+        for (int q = threadIdx.x; q < nk; q += ALM_BLOCK) {
+            double S = 1.0;
+            if (!roma) {
+                for (int ax = 0; ax < 3; ++ax) {
+                    float sa = 0.0f;
+                    for (int d = 0; d < W; ++d) sa += s_g[q][ax][d];
+                    S *= (double)sa;
+                }
+            }
+            s_f[q][3] = (float)(1.0 / S);
+        }
+        __syncthreads();
+        if (mine) {
+            for (int k = 0; k < nk; ++k) {
+                const int dx = X - s_c[k][0] + half, dy = Y - s_c[k][1] + half, dz = Z - s_c[k][2] + half;
+                if ((unsigned)dx >= (unsigned)W || (unsigned)dy >= (unsigned)W || (unsigned)dz >= (unsigned)W) continue;
+                const float w = s_g[k][0][dx] * s_g[k][1][dy] * s_g[k][2][dz] * s_f[k][3];
+                Fx = fmaf(w, s_f[k][0], Fx);
+                Fy = fmaf(w, s_f[k][1], Fy);
+                Fz = fmaf(w, s_f[k][2], Fz);
+            }
+        }
+        __syncthreads();  // the next chunk overwrites the tables
     }
+    if (!mine) return;
     const size_t nb = (size_t)B.bnx * B.bny * B.bnz;
     const size_t c = (size_t)(X - B.x0) + (size_t)B.bnx * ((size_t)(Y - B.y0) + (size_t)B.bny * (size_t)(Z - B.z0));
     R.Fbox[c] = Fx;
