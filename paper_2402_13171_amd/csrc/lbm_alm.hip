@@ -186,9 +186,18 @@ __global__ __launch_bounds__(ALM_BLOCK) void k_alm_points(Geo g, Physics ph, Rot
     const int base = blockIdx.x * ALM_BATCH;
     if (base >= npts) return;  // uniform across the workgroup
     __shared__ double s_corner[ALM_BLOCK][4];  // rho, u of one corner cell per work item
-    __shared__ double s_red[ALM_BATCH][2];
     __shared__ TreePose s_pose[TREE_MAX_NODES];  // turbine: every node's pose at this step
     __shared__ NodeDev s_nodes[TREE_MAX_NODES];  // turbine: the node table
+    // the blade data of the batch's points into registers, in flight with
+    // the sampling
+    double pre_r = 0.0, pre_chord = 0.0, pre_dl = 0.0, pre_twist = 0.0;
+    if (!R.nodes && threadIdx.x < ALM_BATCH && base + (int)threadIdx.x < npts) {
+        const int k = (base + (int)threadIdx.x) % R.n_points;
+        pre_r = R.r[k];
+        pre_chord = R.chord[k];
+        pre_dl = R.dl[k];
+        pre_twist = R.twist[k];
+    }
     if (R.nodes) {
         // one coalesced copy of the node table, so that the pose recursion
         // walks the parent chain in LDS rather than through one dependent
@@ -240,13 +249,14 @@ __global__ __launch_bounds__(ALM_BLOCK) void k_alm_points(Geo g, Physics ph, Rot
                 const int b = p / R.n_points, k = p % R.n_points;
                 const double th = R.azimuth0 + R.omega_rot * (double)t + 2.0 * PI_D * b / R.n_blades;
                 const double ct = cos(th), st = sin(th);
-                const double rr = R.r[k];
+                const double rr = pre_r;  // R.r[k], R.chord[k], ... loaded at the start
+                (void)k;
                 // e_theta = (0, -sin, cos); relative in-plane wind W = W_n e_x - W_t e_theta
                 const double ut = -sm[2] * st + sm[3] * ct;
                 const double wn = sm[1];
                 const double wt = -(ut - R.omega_rot * rr);
                 double Fn, Ft;
-                blade_element(R, rho, wn, wt, R.chord[k], R.dl[k], R.twist[k], R.pitch_deg, R.tip_loss, rr, Fn, Ft);
+                blade_element(R, rho, wn, wt, pre_chord, pre_dl, pre_twist, R.pitch_deg, R.tip_loss, rr, Fn, Ft);
                 Fp[0] = Fn;
                 Fp[1] = -Ft * st;
                 Fp[2] = Ft * ct;
@@ -302,21 +312,17 @@ __global__ __launch_bounds__(ALM_BLOCK) void k_alm_points(Geo g, Physics ph, Rot
                 if (!R.nodes) R.pt_force[3 * p + ax] = Fp[ax];
             }
         }
-        s_red[threadIdx.x][0] = accT;
-        s_red[threadIdx.x][1] = accQ;
-    }
-    __syncthreads();
-    // deterministic FP64 tree over the batch
-    for (int s = ALM_BATCH / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s) {
-            s_red[threadIdx.x][0] += s_red[threadIdx.x + s][0];
-            s_red[threadIdx.x][1] += s_red[threadIdx.x + s][1];
+        // thrust and torque of the batch: the same pairwise tree in FP64 as
+        // an LDS reduction (lane i adds lane i + s for s = 16, 8, 4, 2, 1), in
+        // registers across the batch's 32 lanes of the first wave
+        for (int s = ALM_BATCH / 2; s > 0; s >>= 1) {
+            accT += __shfl_down(accT, s);
+            accQ += __shfl_down(accQ, s);
         }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        R.loads[3 + 2 * blockIdx.x] = s_red[0][0];
-        R.loads[4 + 2 * blockIdx.x] = s_red[0][1];
+        if (threadIdx.x == 0) {
+            R.loads[3 + 2 * blockIdx.x] = accT;
+            R.loads[4 + 2 * blockIdx.x] = accQ;
+        }
     }
 }
 
