@@ -14,6 +14,21 @@ __device__ __forceinline__ size_t cidx(const Geo &g, int x, int y, int z) {
     return ((size_t)z * g.ny + y) * g.nx + x;
 }
 
+// Blocked population layout: the x rows are cut into blocks of BLK cells, and
+// a block keeps its 27 directions one after the other, BLK values each:
+// store[z][y][x / BLK][i][x % BLK] (rows padded to g.nbx whole blocks). A wave
+// of 64 cells of one row then reads and writes one contiguous 27 BLK region
+// in an even step, instead of 27 streams spread over the whole store.
+constexpr int BLK = 64;
+constexpr int BLK_SLOTS = 27 * BLK;
+__device__ __forceinline__ size_t slot_idx(const Geo &g, int i, int x, int y, int z) {
+    return (((size_t)z * g.ny + y) * g.nbx + (size_t)(x >> 6)) * BLK_SLOTS + (size_t)(i * BLK + (x & (BLK - 1)));
+}
+// element offset of cell x's slot 0 within its row of blocks
+__device__ __forceinline__ uint32_t row_xpart(int x) {
+    return (uint32_t)(x >> 6) * (uint32_t)BLK_SLOTS + (uint32_t)(x & (BLK - 1));
+}
+
 __device__ __forceinline__ float phi1(int c, float u) {
     return c == 0 ? (2.0f / 3.0f - u * u) : 0.5f * (1.0f / 3.0f + u * u + c * u);
 }
@@ -34,7 +49,7 @@ __device__ __forceinline__ float read_swapped(const Geo &g, int x, int y, int z)
     bool refl = false;
     if (cz != 0 && (sz < 0 || sz >= g.nz)) {
         const int bc = sz < 0 ? g.bc_zlo : g.bc_zhi;
-        if (bc == BC_NOSLIP) return Store<T>::ld(pops + (size_t)I * g.P + cidx(g, x, y, z));
+        if (bc == BC_NOSLIP) return Store<T>::ld(pops + slot_idx(g, I, x, y, z));
         if (bc == BC_FREESLIP) {
             refl = true;
             sz = z;
@@ -54,7 +69,7 @@ __device__ __forceinline__ float read_swapped(const Geo &g, int x, int y, int z)
             return Store<T>::ld(G + (size_t)(ii / 3) * g.ny * g.nz + sy + (size_t)g.ny * sz);
         }
     }
-    return Store<T>::ld(pops + (size_t)(26 - ii) * g.P + cidx(g, sx, sy, sz));
+    return Store<T>::ld(pops + slot_idx(g, 26 - ii, sx, sy, sz));
 }
 
 // Odd-step push of the post-collision deviation of direction I.
@@ -67,7 +82,7 @@ __device__ __forceinline__ void write_odd(const Geo &g, int x, int y, int z, flo
     if (cz != 0 && (tz < 0 || tz >= g.nz)) {
         const int bc = tz < 0 ? g.bc_zlo : g.bc_zhi;
         if (bc == BC_NOSLIP) {
-            Store<T>::st(pops + (size_t)(26 - I) * g.P + cidx(g, x, y, z), v);
+            Store<T>::st(pops + slot_idx(g, 26 - I, x, y, z), v);
             return;
         }
         if (bc == BC_FREESLIP) {
@@ -82,7 +97,7 @@ __device__ __forceinline__ void write_odd(const Geo &g, int x, int y, int z, flo
         if (g.bc_x != BC_PERIODIC) return;
         tx = wrapi(tx, g.nx);
     }
-    Store<T>::st(pops + (size_t)(refl ? RI : I) * g.P + cidx(g, tx, ty, tz), v);
+    Store<T>::st(pops + slot_idx(g, refl ? RI : I, tx, ty, tz), v);
 }
 
 // Force on a cell: uniform part + optional dense field + rotor boxes.
@@ -117,125 +132,142 @@ __device__ __forceinline__ float omega1_of(const CellMoments &m, const Physics &
 
 template <typename T, int I>
 struct Unroll {
-    // load/store helpers unrolled over the 27 directions at compile time
-    static __device__ __forceinline__ void read_natural(const Geo &g, size_t cell, float *d) {
-        d[I] = Store<T>::ld((const T *)g.pops + (size_t)I * g.P + cell);
-        Unroll<T, I + 1>::read_natural(g, cell, d);
+    // load/store helpers unrolled over the 27 directions at compile time;
+    // s0 is the element index of the cell's slot 0 (slot_idx(g, 0, x, y, z))
+    static __device__ __forceinline__ void read_natural(const Geo &g, size_t s0, float *d) {
+        d[I] = Store<T>::ld((const T *)g.pops + s0 + I * BLK);
+        Unroll<T, I + 1>::read_natural(g, s0, d);
     }
     static __device__ __forceinline__ void read_sw(const Geo &g, int x, int y, int z, float *d) {
         d[I] = read_swapped<T, I>(g, x, y, z);
         Unroll<T, I + 1>::read_sw(g, x, y, z, d);
     }
-    static __device__ __forceinline__ void write_swap_local(const Geo &g, size_t cell, const float *o) {
-        Store<T>::st((T *)g.pops + (size_t)(26 - I) * g.P + cell, o[I]);
-        Unroll<T, I + 1>::write_swap_local(g, cell, o);
+    static __device__ __forceinline__ void write_swap_local(const Geo &g, size_t s0, const float *o) {
+        Store<T>::st((T *)g.pops + s0 + (26 - I) * BLK, o[I]);
+        Unroll<T, I + 1>::write_swap_local(g, s0, o);
     }
     static __device__ __forceinline__ void write_push(const Geo &g, int x, int y, int z, const float *o) {
         write_odd<T, I>(g, x, y, z, o[I]);
         Unroll<T, I + 1>::write_push(g, x, y, z, o);
     }
-    // periodic fast paths: row offsets for dy,dz in {-1,0,1}
-    static __device__ __forceinline__ void read_periodic(const Geo &g, const int *xs, const size_t *rows, float *d) {
-        constexpr int cx = cx_of(I), cy = cy_of(I), cz = cz_of(I);
-        // source x - c: xs[1 - cx], rows[(1 - cy) + 3 (1 - cz)]
-        d[I] = Store<T>::ld((const T *)g.pops + (size_t)(26 - I) * g.P + rows[(1 - cy) + 3 * (1 - cz)] + xs[1 - cx]);
-        Unroll<T, I + 1>::read_periodic(g, xs, rows, d);
-    }
-    static __device__ __forceinline__ void write_periodic(const Geo &g, const int *xs, const size_t *rows, const float *o) {
-        constexpr int cx = cx_of(I), cy = cy_of(I), cz = cz_of(I);
-        Store<T>::st((T *)g.pops + (size_t)I * g.P + rows[(1 + cy) + 3 * (1 + cz)] + xs[1 + cx], o[I]);
-        Unroll<T, I + 1>::write_periodic(g, xs, rows, o);
-    }
 };
-// Fast-path variants with 32-bit byte offsets from per-plane base pointers:
-// the plane base is uniform across the wave (scalar registers), so each access
-// is one global load/store with a 32-bit vector offset. Valid while
-// n * sizeof(T) < 2^32 (checked on the host, which otherwise uses the
-// 64-bit general path).
-// FP32 storage addresses every access with a per-lane 64-bit address instead
-// (global_load v, v[a:b], off): on MI355X the 27-plane pattern of a 512^3
-// step moved about 2 % more bytes per second that way, for the stream-collide
-// kernel and a bare copy of its accesses alike; with 16-bit storage the
-// scalar-base form was the faster one (by about 1.5 %) and stays.
-typedef __attribute__((address_space(1))) float global_f32;
-__device__ __forceinline__ global_f32 *lane_addr_f32(const Geo &g, int i, uint32_t boff) {
-    uint64_t a = (uint64_t)((float *)g.pops + ((size_t)i * g.P + (size_t)(boff / 4u)));
-    asm volatile("" : "+v"(a));  // keep the sum per lane (the compiler would fold it back to a scalar base)
-    return (global_f32 *)a;
-}
-template <typename T>
-__device__ __forceinline__ float ld_plane(const Geo &g, int i, uint32_t boff) {
-    if constexpr (sizeof(T) == 4) return *lane_addr_f32(g, i, boff);
-    else return Store<T>::ld((const T *)((const char *)g.pops + (size_t)i * g.P * sizeof(T) + boff));
-}
-template <typename T>
-__device__ __forceinline__ void st_plane(const Geo &g, int i, uint32_t boff, float v) {
-    if constexpr (sizeof(T) == 4) *lane_addr_f32(g, i, boff) = v;
-    else Store<T>::st((T *)((char *)g.pops + (size_t)i * g.P * sizeof(T) + boff), v);
-}
-
-template <typename T, int I>
-struct Unroll32 {
-    static __device__ __forceinline__ void read_natural(const Geo &g, uint32_t boff, float *d) {
-        d[I] = ld_plane<T>(g, I, boff);
-        Unroll32<T, I + 1>::read_natural(g, boff, d);
-    }
-    static __device__ __forceinline__ void write_swap_local(const Geo &g, uint32_t boff, const float *o) {
-        st_plane<T>(g, 26 - I, boff, o[I]);
-        Unroll32<T, I + 1>::write_swap_local(g, boff, o);
-    }
-    // rows[(dy+1) + 3 (dz+1)] and xs[dx+1] are element offsets of the wrapped neighbours
-    static __device__ __forceinline__ void read_periodic(const Geo &g, const uint32_t *xs, const uint32_t *rows,
-                                                         float *d) {
-        constexpr int cx = cx_of(I), cy = cy_of(I), cz = cz_of(I);
-        const uint32_t boff = (rows[(1 - cy) + 3 * (1 - cz)] + xs[1 - cx]) * (uint32_t)sizeof(T);
-        d[I] = ld_plane<T>(g, 26 - I, boff);
-        Unroll32<T, I + 1>::read_periodic(g, xs, rows, d);
-    }
-    static __device__ __forceinline__ void write_periodic(const Geo &g, const uint32_t *xs, const uint32_t *rows,
-                                                          const float *o) {
-        constexpr int cx = cx_of(I), cy = cy_of(I), cz = cz_of(I);
-        const uint32_t boff = (rows[(1 + cy) + 3 * (1 + cz)] + xs[1 + cx]) * (uint32_t)sizeof(T);
-        st_plane<T>(g, I, boff, o[I]);
-        Unroll32<T, I + 1>::write_periodic(g, xs, rows, o);
-    }
-    // the nine directions with c_x = CX only
-    template <int CX>
-    static __device__ __forceinline__ void write_periodic_cx(const Geo &g, const uint32_t *xs, const uint32_t *rows,
-                                                             const float *o) {
-        constexpr int cx = cx_of(I), cy = cy_of(I), cz = cz_of(I);
-        if constexpr (cx == CX) {
-            const uint32_t boff = (rows[(1 + cy) + 3 * (1 + cz)] + xs[1 + cx]) * (uint32_t)sizeof(T);
-            st_plane<T>(g, I, boff, o[I]);
-        }
-        Unroll32<T, I + 1>::template write_periodic_cx<CX>(g, xs, rows, o);
-    }
-};
-template <typename T>
-struct Unroll32<T, 27> {
-    static __device__ __forceinline__ void read_natural(const Geo &, uint32_t, float *) {}
-    static __device__ __forceinline__ void write_swap_local(const Geo &, uint32_t, const float *) {}
-    static __device__ __forceinline__ void read_periodic(const Geo &, const uint32_t *, const uint32_t *, float *) {}
-    static __device__ __forceinline__ void write_periodic(const Geo &, const uint32_t *, const uint32_t *, const float *) {}
-    template <int CX>
-    static __device__ __forceinline__ void write_periodic_cx(const Geo &, const uint32_t *, const uint32_t *,
-                                                             const float *) {}
-};
-
 template <typename T>
 struct Unroll<T, 27> {
     static __device__ __forceinline__ void read_natural(const Geo &, size_t, float *) {}
     static __device__ __forceinline__ void read_sw(const Geo &, int, int, int, float *) {}
     static __device__ __forceinline__ void write_swap_local(const Geo &, size_t, const float *) {}
     static __device__ __forceinline__ void write_push(const Geo &, int, int, int, const float *) {}
-    static __device__ __forceinline__ void read_periodic(const Geo &, const int *, const size_t *, float *) {}
-    static __device__ __forceinline__ void write_periodic(const Geo &, const int *, const size_t *, const float *) {}
+};
+
+// Fast path (no boundary rules in the addressing): a tile lies in one z
+// plane, so the bases of the z planes z - 1, z, z + 1 are uniform across the
+// workgroup (scalar registers) and every access is one global load or store
+// with that base, a 32-bit lane offset and the direction's slot as the
+// constant offset. Nbr holds, for cell (x, y, z), the element offsets within
+// a z plane of the rows y - 1, y, y + 1 (ys) and of the cells x - 1, x, x + 1
+// within a row (xo), wrapped periodically, and the element bases of the z
+// planes z - 1, z, z + 1 (zb), wrapped. Valid while a z plane of blocks has
+// fewer than 2^32 bytes (checked on the host).
+struct Nbr {
+    uint32_t ys[3], xo[3];
+    size_t zb[3];
+};
+__device__ __forceinline__ void fast_nbr(const Geo &g, int x, int y, int z, Nbr &n) {
+    const int xm = x == 0 ? g.nx - 1 : x - 1, xp = x == g.nx - 1 ? 0 : x + 1;
+    n.xo[0] = row_xpart(xm);
+    n.xo[1] = row_xpart(x);
+    n.xo[2] = row_xpart(xp);
+    const uint32_t rowlen = (uint32_t)g.nbx * (uint32_t)BLK_SLOTS, yr = (uint32_t)y * rowlen;
+    n.ys[0] = y == 0 ? (uint32_t)(g.ny - 1) * rowlen : yr - rowlen;
+    n.ys[1] = yr;
+    n.ys[2] = y == g.ny - 1 ? 0u : yr + rowlen;
+    const size_t zplane = (size_t)g.ny * rowlen;
+    n.zb[0] = (size_t)(z == 0 ? g.nz - 1 : z - 1) * zplane;
+    n.zb[1] = (size_t)z * zplane;
+    n.zb[2] = (size_t)(z == g.nz - 1 ? 0 : z + 1) * zplane;
+}
+// FP32 storage addresses every fast-path access with a per-lane 64-bit
+// address (global_load v, v[a:b], off) instead of the scalar base + 32-bit
+// offset form, which 16-bit storage keeps.
+typedef __attribute__((address_space(1))) float global_f32;
+__device__ __forceinline__ global_f32 *lane_f32(const void *p) {
+    uint64_t a = (uint64_t)p;
+    asm volatile("" : "+v"(a));  // keep the sum per lane (the compiler would fold it back to a scalar base)
+    return (global_f32 *)a;
+}
+// slot i of the cell at (x + dx, y + dy, z + dz), dx, dy, dz in {-1, 0, 1}
+template <typename T>
+__device__ __forceinline__ float ld_nbr(const Geo &g, const Nbr &n, int dx, int dy, int dz, int i) {
+    const char *plane = (const char *)g.pops + n.zb[dz + 1] * sizeof(T) + (size_t)i * BLK * sizeof(T);
+    const char *p = plane + (n.ys[dy + 1] + n.xo[dx + 1]) * (uint32_t)sizeof(T);
+    if constexpr (sizeof(T) == 4) return *lane_f32(p);
+    else return Store<T>::ld((const T *)p);
+}
+template <typename T>
+__device__ __forceinline__ void st_nbr(const Geo &g, const Nbr &n, int dx, int dy, int dz, int i, float v) {
+    char *plane = (char *)g.pops + n.zb[dz + 1] * sizeof(T) + (size_t)i * BLK * sizeof(T);
+    char *p = plane + (n.ys[dy + 1] + n.xo[dx + 1]) * (uint32_t)sizeof(T);
+    if constexpr (sizeof(T) == 4) *lane_f32(p) = v;
+    else Store<T>::st((T *)p, v);
+}
+// the cell's own slot 0 (its 27 slots follow at strides of BLK elements)
+__device__ __forceinline__ global_f32 *own_f32(const Geo &g, const Nbr &n) {
+    return lane_f32((const float *)g.pops + n.zb[1] + n.ys[1] + n.xo[1]);
+}
+
+template <typename T, int I>
+struct Unroll32 {
+    // even step: the cell's own slots
+    static __device__ __forceinline__ void read_natural(const Geo &g, const Nbr &n, float *d) {
+        if constexpr (sizeof(T) == 4) {  // one per-lane base, the slots at constant offsets
+            const global_f32 *b = own_f32(g, n);
+#pragma unroll
+            for (int i = 0; i < 27; ++i) d[i] = b[i * BLK];
+        } else {
+            d[I] = ld_nbr<T>(g, n, 0, 0, 0, I);
+            Unroll32<T, I + 1>::read_natural(g, n, d);
+        }
+    }
+    static __device__ __forceinline__ void write_swap_local(const Geo &g, const Nbr &n, const float *o) {
+        if constexpr (sizeof(T) == 4) {
+            global_f32 *b = own_f32(g, n);
+#pragma unroll
+            for (int i = 0; i < 27; ++i) b[(26 - i) * BLK] = o[i];
+        } else {
+            st_nbr<T>(g, n, 0, 0, 0, 26 - I, o[I]);
+            Unroll32<T, I + 1>::write_swap_local(g, n, o);
+        }
+    }
+    // odd step: slot 26 - I of x - c_I, and the push into slot I of x + c_I
+    static __device__ __forceinline__ void read_periodic(const Geo &g, const Nbr &n, float *d) {
+        d[I] = ld_nbr<T>(g, n, -cx_of(I), -cy_of(I), -cz_of(I), 26 - I);
+        Unroll32<T, I + 1>::read_periodic(g, n, d);
+    }
+    static __device__ __forceinline__ void write_periodic(const Geo &g, const Nbr &n, const float *o) {
+        st_nbr<T>(g, n, cx_of(I), cy_of(I), cz_of(I), I, o[I]);
+        Unroll32<T, I + 1>::write_periodic(g, n, o);
+    }
+    // the nine directions with c_x = CX only
+    template <int CX>
+    static __device__ __forceinline__ void write_periodic_cx(const Geo &g, const Nbr &n, const float *o) {
+        if constexpr (cx_of(I) == CX) st_nbr<T>(g, n, cx_of(I), cy_of(I), cz_of(I), I, o[I]);
+        Unroll32<T, I + 1>::template write_periodic_cx<CX>(g, n, o);
+    }
+};
+template <typename T>
+struct Unroll32<T, 27> {
+    static __device__ __forceinline__ void read_natural(const Geo &, const Nbr &, float *) {}
+    static __device__ __forceinline__ void write_swap_local(const Geo &, const Nbr &, const float *) {}
+    static __device__ __forceinline__ void read_periodic(const Geo &, const Nbr &, float *) {}
+    static __device__ __forceinline__ void write_periodic(const Geo &, const Nbr &, const float *) {}
+    template <int CX>
+    static __device__ __forceinline__ void write_periodic_cx(const Geo &, const Nbr &, const float *) {}
 };
 
 // ------------------------------------------------------------ readers
 template <typename T, int PAR>
 __device__ __forceinline__ void read_cell(const Geo &g, size_t cell, int x, int y, int z, float *d) {
-    if (PAR == 0) Unroll<T, 0>::read_natural(g, cell, d);
+    if (PAR == 0) Unroll<T, 0>::read_natural(g, slot_idx(g, 0, x, y, z), d);
     else Unroll<T, 0>::read_sw(g, x, y, z, d);
 }
 

@@ -42,7 +42,9 @@ struct lbm_ctx {
     lbm_config cfg{};
     hipStream_t stream = nullptr;
     bool own_stream = false;
-    size_t n = 0, P = 0, esize = 4;
+    size_t n = 0, esize = 4;
+    int nbx = 0;          // blocks of 64 cells per x row
+    size_t zplane = 0;    // elements per z plane of the blocked store
     size_t pop_bytes = 0, aux_bytes = 0;
     size_t off_ghost = 0, off_uin = 0, off_part = 0, off_flag = 0;
     void *pops = nullptr, *aux = nullptr;
@@ -129,7 +131,7 @@ float *uin_plane(const lbm_ctx *c, long t) {
 Geo geo_of(const lbm_ctx *c) {
     Geo g{};
     g.pops = c->pops;
-    g.P = c->P;
+    g.nbx = c->nbx;
     g.nx = c->cfg.nx;
     g.ny = c->cfg.ny;
     g.nz = c->cfg.nz;
@@ -163,15 +165,17 @@ Physics physics_of(const lbm_ctx *c) {
     return ph;
 }
 
-// The fast stream-collide path needs 32-bit byte offsets within one
-// population plane; with them, a periodic box runs it everywhere and an open
-// one on every cell off the z walls (odd steps). Otherwise: the general path.
+// The fast stream-collide path needs 32-bit byte offsets within one z plane
+// of the blocked store; with them, a periodic box runs it everywhere and an
+// open one on every cell off the z walls (odd steps). Otherwise: the general
+// path.
+bool fast_offsets_fit(const lbm_ctx *c) { return c->zplane * c->esize < ((size_t)1 << 32); }
 bool general_bc(const lbm_ctx *c) {
     return c->cfg.bc_x != LBM_BC_PERIODIC || c->cfg.bc_z_lo != LBM_BC_PERIODIC || c->cfg.bc_z_hi != LBM_BC_PERIODIC ||
-           c->P * c->esize >= ((size_t)1 << 32);
+           !fast_offsets_fit(c);
 }
 static int sc_mode(const lbm_ctx *c) {
-    if (c->cfg.general_path || c->P * c->esize >= ((size_t)1 << 32)) return SC_GENERAL;
+    if (c->cfg.general_path || !fast_offsets_fit(c)) return SC_GENERAL;
     return general_bc(c) ? SC_SPLIT : SC_FAST;
 }
 
@@ -302,8 +306,9 @@ int lbm_create(const lbm_config *cfg, lbm_ctx **out) {
         x->cfg = c;
         x->n = n;
         x->esize = c.storage == LBM_F32 ? 4 : 2;
-        x->P = round_up(n * x->esize, 256) / x->esize;
-        x->pop_bytes = 27 * x->P * x->esize;
+        x->nbx = (c.nx + 63) / 64;
+        x->zplane = (size_t)c.ny * (size_t)x->nbx * 27 * 64;
+        x->pop_bytes = round_up((size_t)c.nz * x->zplane * x->esize, 256);
         x->omega2 = c.omega_hi[0] == 0.0 ? 1.0f : (float)c.omega_hi[0];
         for (int k = 0; k < 8; ++k) {
             x->omega_hi[k] = c.omega_hi[k + 1] == 0.0 ? 1.0f : (float)c.omega_hi[k + 1];
@@ -1196,7 +1201,7 @@ int lbm_pattern_probe(lbm_ctx *c, int parity) {
         int rc = ready(c);
         if (rc) return rc;
         if (parity != 0 && parity != 1) return fail(c, LBM_EINVAL, "parity must be 0 or 1");
-        if (c->P * c->esize >= ((size_t)1 << 32)) return fail(c, LBM_EINVAL, "probe needs 32-bit plane offsets");
+        if (!fast_offsets_fit(c)) return fail(c, LBM_EINVAL, "probe needs 32-bit offsets within a z plane");
         if (launch_pattern_probe((int)c->cfg.storage, parity, geo_of(c), c->stream))
             return fail(c, LBM_EHIP, "probe launch failed");
         return LBM_OK;
@@ -1267,7 +1272,7 @@ int lbm_set_closure_weights(lbm_ctx *c, const float *w, size_t n) {
 }
 
 // checkpoint header: magic, time, parity, storage, force-box bytes, nx, ny, nz
-constexpr long STATE_MAGIC = 0x4c424d32L;
+constexpr long STATE_MAGIC = 0x4c424d33L;  // blocked population layout
 
 // bytes of the force boxes of the active rotor / turbine slots (slot order)
 static size_t box_state_bytes(const lbm_ctx *c) {

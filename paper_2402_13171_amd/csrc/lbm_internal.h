@@ -50,8 +50,8 @@ void mlp_pack(const float *blob, MlpDev *out);
 
 // Everything a lattice kernel needs, passed by value.
 struct Geo {
-    void *pops;          // population store (storage type)
-    size_t P;            // plane stride in elements
+    void *pops;          // population store (storage type), blocked layout (lbm_access.h)
+    int nbx;             // blocks of 64 cells per x row (nx rounded up)
     int nx, ny, nz;
     int bc_x, bc_zlo, bc_zhi;
     const float *uin_rd; // inlet velocity plane [3][ny*nz] of the streaming a swapped-layout read completes

@@ -53,7 +53,7 @@ __device__ __forceinline__ void odd_boundary_extras(const Geo &g, int x, int y, 
                 }
             }
             const int sy = wrapi(y - cy, g.ny);
-            Store<T>::st(pops + (size_t)I * g.P + cidx(g, 0, y, z), inlet_dev(g, g.uin_wr, ii, sy, sz));
+            Store<T>::st(pops + slot_idx(g, I, 0, y, z), inlet_dev(g, g.uin_wr, ii, sy, sz));
         }
     }
     if (x == g.nx - 1) {
@@ -67,12 +67,12 @@ __device__ __forceinline__ void odd_boundary_extras(const Geo &g, int x, int y, 
                 const int bc = tz < 0 ? g.bc_zlo : g.bc_zhi;
                 if (bc == BC_NOSLIP) continue;
                 if (bc == BC_FREESLIP) {
-                    Store<T>::st(pops + (size_t)refl_z(J) * g.P + cidx(g, x, ty, z), o[J]);
+                    Store<T>::st(pops + slot_idx(g, refl_z(J), x, ty, z), o[J]);
                     continue;
                 }
                 tz = wrapi(tz, g.nz);
             }
-            Store<T>::st(pops + (size_t)J * g.P + cidx(g, x, ty, tz), o[J]);
+            Store<T>::st(pops + slot_idx(g, J, x, ty, tz), o[J]);
         }
     }
 }
@@ -99,36 +99,18 @@ __device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned total) {
 // z plane, tw in {64, 128, 256}; a wave is a 64-cell row segment. Wide tiles
 // keep the cache lines that odd-step shifted accesses split between
 // neighbouring row segments inside one workgroup.
-// A copy of g whose plane stride the compiler cannot see through (an empty
+// A copy of g whose store base the compiler cannot see through (an empty
 // asm that claims to rewrite the scalar register pair), so that addresses
 // built from it are recomputed rather than kept live.
 __device__ __forceinline__ Geo with_opaque_stride(const Geo &g) {
     Geo r = g;
-    size_t P = r.P;
-    asm volatile("" : "+s"(P));
-    r.P = P;
+    void *p = r.pops;
+    asm volatile("" : "+s"(p));
+    r.pops = p;
     return r;
 }
 
 __device__ __forceinline__ void opaque_v(uint32_t &v) { asm volatile("" : "+v"(v)); }
-
-// Element offsets of the periodic neighbours of (x, y, z): xs[dx + 1] and
-// rows[(dy + 1) + 3 (dz + 1)] for dx, dy, dz in {-1, 0, 1}.
-__device__ __forceinline__ void periodic_offsets(const Geo &g, int x, int y, int z, uint32_t xs[3], uint32_t rows[9]) {
-    xs[0] = x == 0 ? g.nx - 1 : x - 1;
-    xs[1] = x;
-    xs[2] = x == g.nx - 1 ? 0 : x + 1;
-    // row starts y nx and plane starts z nx ny of the wrapped neighbours:
-    // two multiplies, the rest adds and selects
-    const uint32_t nx = (uint32_t)g.nx, plane = nx * (uint32_t)g.ny;
-    const uint32_t yr = (uint32_t)y * nx, zp = (uint32_t)z * plane;
-    const uint32_t ys[3] = {y == 0 ? plane - nx : yr - nx, yr, y == g.ny - 1 ? 0u : yr + nx};
-    const uint32_t zs[3] = {z == 0 ? (uint32_t)(g.nz - 1) * plane : zp - plane, zp, z == g.nz - 1 ? 0u : zp + plane};
-#pragma unroll
-    for (int b = 0; b < 3; ++b)
-#pragma unroll
-        for (int a = 0; a < 3; ++a) rows[a + 3 * b] = zs[b] + ys[a];
-}
 
 // Odd-step sources outside the box in x for a cell off the z walls (z wraps
 // if periodic): x = -1 gives the inlet equilibrium, x = nx the ghost plane.
@@ -181,29 +163,30 @@ constexpr int STAGE_W = 258;
 // the launch chooses the staged kernels when the tiles allow it
 static bool odd_staged_ok(const Geo &g, unsigned tw_log2) { return tw_log2 == 8u && (g.nx % 256) == 0; }
 template <typename T, bool XO>
-__device__ __forceinline__ void write_odd_staged(const Geo &g, const uint32_t *xs, const uint32_t *rows,
-                                                 const float *o, T *stage) {
+__device__ __forceinline__ void write_odd_staged(const Geo &g, int x, const Nbr &n, const float *o, T *stage) {
     const uint32_t t = threadIdx.x;
 #pragma unroll
     for (int j = 0; j < 9; ++j) {
         Store<T>::st(stage + j * STAGE_W + t, o[3 * j]);                // c_x = -1, source lane t
         Store<T>::st(stage + (9 + j) * STAGE_W + t + 2, o[3 * j + 2]);  // c_x = +1, source lane t
     }
-    Unroll32<T, 0>::template write_periodic_cx<0>(g, xs, rows, o);
+    Unroll32<T, 0>::template write_periodic_cx<0>(g, n, o);
     __syncthreads();
-    const uint32_t nx = (uint32_t)g.nx, x = xs[1], x0 = x - t;
-    const uint32_t x_lo = x0 == 0u ? nx - 1u : x0 - 1u;      // x0 - 1, wrapped
-    const uint32_t x_hi = x0 + 256u == nx ? 0u : x0 + 256u;  // x0 + 256, wrapped
+    const int x0 = x - (int)t;
+    const int x_lo = x0 == 0 ? g.nx - 1 : x0 - 1;      // x0 - 1, wrapped
+    const int x_hi = x0 + 256 == g.nx ? 0 : x0 + 256;  // x0 + 256, wrapped
     const bool last = t == 255u, first = t == 0u;
-    const uint32_t xm = last ? x_lo : x, im = last ? 0u : t + 1u;     // c_x = -1
-    const uint32_t xp = first ? x_hi : x, ip = first ? 257u : t + 1u;  // c_x = +1
-    const bool keep_m = !(XO && last && x0 == 0u), keep_p = !(XO && first && x0 + 256u == nx);
+    const uint32_t xm = last ? row_xpart(x_lo) : n.xo[1], im = last ? 0u : t + 1u;   // c_x = -1
+    const uint32_t xp = first ? row_xpart(x_hi) : n.xo[1], ip = first ? 257u : t + 1u;  // c_x = +1
+    const bool keep_m = !(XO && last && x0 == 0), keep_p = !(XO && first && x0 + 256 == g.nx);
 #pragma unroll
     for (int j = 0; j < 9; ++j) {
-        // directions 3j (c_x = -1) and 3j + 2 (c_x = +1) share c_y, c_z: row rows[j]
-        const uint32_t r = rows[j];
-        const char *pm = (const char *)g.pops + (size_t)(3 * j) * g.P * sizeof(T);
-        const char *pp = (const char *)g.pops + (size_t)(3 * j + 2) * g.P * sizeof(T);
+        // directions 3j (c_x = -1) and 3j + 2 (c_x = +1) share c_y, c_z: the
+        // row y + c_y of the z plane z + c_z
+        const int cy = cy_of(3 * j), cz = cz_of(3 * j);
+        const uint32_t r = n.ys[1 + cy];
+        const char *pm = (const char *)g.pops + (n.zb[1 + cz] + (size_t)(3 * j) * BLK) * sizeof(T);
+        const char *pp = (const char *)g.pops + (n.zb[1 + cz] + (size_t)(3 * j + 2) * BLK) * sizeof(T);
         const T vm = stage[j * STAGE_W + im], vp = stage[(9 + j) * STAGE_W + ip];
         if (keep_m) *(T *)(pm + (r + xm) * (uint32_t)sizeof(T)) = vm;
         if (keep_p) *(T *)(pp + (r + xp) * (uint32_t)sizeof(T)) = vp;
@@ -215,16 +198,18 @@ __device__ __forceinline__ void cell_update(const Geo &g, const Physics &ph, int
                                             MlpLds &mlp_lds, T *stage = nullptr) {
     if (CL != CL_MLP && !valid) return;
     const size_t cell = cidx(g, x, y, z);
-    // fast path (no boundary rules): 32-bit offsets, see Unroll32
-    const uint32_t cell32 = (uint32_t)cell;
     float d[27];
-    uint32_t xs[3], rows[9];
+    Nbr n;  // fast path (no boundary rules in the addressing), see Unroll32
     if (PAR == 0) {
-        if (BCG) Unroll<T, 0>::read_natural(g, cell, d);
-        else Unroll32<T, 0>::read_natural(g, cell32 * (uint32_t)sizeof(T), d);
+        if (BCG) {
+            Unroll<T, 0>::read_natural(g, slot_idx(g, 0, x, y, z), d);
+        } else {
+            fast_nbr(g, x, y, z, n);
+            Unroll32<T, 0>::read_natural(g, n, d);
+        }
     } else if (!BCG) {
-        periodic_offsets(g, x, y, z, xs, rows);
-        Unroll32<T, 0>::read_periodic(g, xs, rows, d);
+        fast_nbr(g, x, y, z, n);
+        Unroll32<T, 0>::read_periodic(g, n, d);
         if (XO) open_x_sources<T>(g, x, y, z, d);
     } else {
         Unroll<T, 0>::read_sw(g, x, y, z, d);
@@ -249,29 +234,20 @@ __device__ __forceinline__ void cell_update(const Geo &g, const Physics &ph, int
     if (CL == CL_MLP && !valid) return;
     sr_round_cell<T>(o, (uint32_t)cell, ph.sr_seed);
     // the closure variant needs scalar registers for the network: an opaque
-    // copy of the plane stride makes the compiler rebuild the plane bases of
-    // the stores here instead of holding them from the loads on
-    // (and the 32-bit offsets are re-declared in this block, where the store
-    // instructions can then take them as 32-bit vector offsets)
+    // copy of the store base makes the compiler rebuild the z-plane bases of
+    // the stores here instead of holding them from the loads on, and the
+    // offsets are rebuilt from x, y, z rather than held through the network
     const Geo gw = CL == CL_MLP ? with_opaque_stride(g) : g;
-    // (the odd step rebuilds its neighbour offsets from x, y, z rather than
-    // holding twelve registers through the network)
-    uint32_t boff = cell32 * (uint32_t)sizeof(T);
     if (CL == CL_MLP && !BCG) {
-        if (PAR == 0) {
-            opaque_v(boff);
-        } else {
-            uint32_t xo = (uint32_t)x, yo = (uint32_t)y, zo = (uint32_t)z;
-            opaque_v(xo);
-            opaque_v(yo);
-            opaque_v(zo);
-            periodic_offsets(g, (int)xo, (int)yo, (int)zo, xs, rows);
-        }
+        uint32_t xo = (uint32_t)x, yo = (uint32_t)y;
+        opaque_v(xo);
+        opaque_v(yo);
+        fast_nbr(g, (int)xo, (int)yo, z, n);
     }
 
     if (PAR == 0) {
-        if (BCG) Unroll<T, 0>::write_swap_local(g, cell, o);
-        else Unroll32<T, 0>::write_swap_local(gw, boff, o);
+        if (BCG) Unroll<T, 0>::write_swap_local(g, slot_idx(g, 0, x, y, z), o);
+        else Unroll32<T, 0>::write_swap_local(gw, n, o);
         if ((BCG || XO) && g.bc_x == BC_INOUT && x == g.nx - 1) {
             T *G = (T *)g.ghost;
 #pragma unroll
@@ -280,16 +256,16 @@ __device__ __forceinline__ void cell_update(const Geo &g, const Physics &ph, int
         }
     } else if (!BCG) {
         if constexpr (LS) {
-            write_odd_staged<T, XO>(gw, xs, rows, o, stage);
+            write_odd_staged<T, XO>(gw, x, n, o, stage);
             if (XO) odd_boundary_extras<T>(g, x, y, z, o);
         } else if (XO) {
             // pushes out of the box through x are dropped
-            if (x != 0) Unroll32<T, 0>::template write_periodic_cx<-1>(gw, xs, rows, o);
-            Unroll32<T, 0>::template write_periodic_cx<0>(gw, xs, rows, o);
-            if (x != g.nx - 1) Unroll32<T, 0>::template write_periodic_cx<1>(gw, xs, rows, o);
+            if (x != 0) Unroll32<T, 0>::template write_periodic_cx<-1>(gw, n, o);
+            Unroll32<T, 0>::template write_periodic_cx<0>(gw, n, o);
+            if (x != g.nx - 1) Unroll32<T, 0>::template write_periodic_cx<1>(gw, n, o);
             odd_boundary_extras<T>(g, x, y, z, o);
         } else {
-            Unroll32<T, 0>::write_periodic(gw, xs, rows, o);
+            Unroll32<T, 0>::write_periodic(gw, n, o);
         }
     } else {
         Unroll<T, 0>::write_push(g, x, y, z, o);
@@ -363,19 +339,18 @@ __global__ __launch_bounds__(256) void k_pattern_probe(Geo g, unsigned gx, unsig
     const int z = (int)(tile / (gx * gy));
     if (x >= g.nx || y >= g.ny) return;
     float d[27];
+    Nbr n;
+    fast_nbr(g, x, y, z, n);
     if (PAR == 0) {
-        const uint32_t boff = (uint32_t)cidx(g, x, y, z) * (uint32_t)sizeof(T);
-        Unroll32<T, 0>::read_natural(g, boff, d);
-        Unroll32<T, 0>::write_swap_local(g, boff, d);
+        Unroll32<T, 0>::read_natural(g, n, d);
+        Unroll32<T, 0>::write_swap_local(g, n, d);
     } else {
-        uint32_t xs[3], rows[9];
-        periodic_offsets(g, x, y, z, xs, rows);
-        Unroll32<T, 0>::read_periodic(g, xs, rows, d);
+        Unroll32<T, 0>::read_periodic(g, n, d);
         if constexpr (LS) {
             __shared__ T stage[18 * STAGE_W];
-            write_odd_staged<T, false>(g, xs, rows, d, stage);
+            write_odd_staged<T, false>(g, x, n, d, stage);
         } else {
-            Unroll32<T, 0>::write_periodic(g, xs, rows, d);
+            Unroll32<T, 0>::write_periodic(g, n, d);
         }
     }
 }
@@ -515,12 +490,14 @@ __device__ __forceinline__ double phi1d(int c, double u) {
 template <typename T>
 __device__ __forceinline__ void store_eq(const Geo &g, size_t cell, double rho, double ux, double uy, double uz) {
     T *pops = (T *)g.pops;
+    const int x = (int)(cell % g.nx), y = (int)((cell / g.nx) % g.ny), z = (int)(cell / ((size_t)g.nx * g.ny));
+    const size_t s0 = slot_idx(g, 0, x, y, z);
 #pragma unroll
     for (int i = 0; i < 27; ++i) {
         const double w = (cx_of(i) == 0 ? 2.0 / 3.0 : 1.0 / 6.0) * (cy_of(i) == 0 ? 2.0 / 3.0 : 1.0 / 6.0) *
                          (cz_of(i) == 0 ? 2.0 / 3.0 : 1.0 / 6.0);
         const double fe = rho * phi1d(cx_of(i), ux) * phi1d(cy_of(i), uy) * phi1d(cz_of(i), uz);
-        Store<T>::st(pops + (size_t)i * g.P + cell, (float)(fe - w));
+        Store<T>::st(pops + s0 + (size_t)i * BLK, (float)(fe - w));
     }
 }
 

@@ -1,8 +1,8 @@
-"""Parity at the largest boxes one population plane allows per path (FP32):
-  * 1024 x 1024 x 1016: planes of 4.26e9 bytes, just under 2^32, so the
-    32-bit-offset fast path runs with byte offsets near its limit;
-  * 1024^3: planes of exactly 2^32 bytes, so every cell takes the 64-bit
-    general path (116 GB of populations).
+"""Parity at the largest boxes (FP32, 113-116 GB of populations in the
+blocked store, far past 2^32 bytes): the fast path, whose lane offsets are
+32-bit within a z plane of blocks (113 MB here) and whose z-plane bases are
+64-bit, on 1024 x 1024 x 1016 and 1024^3, and the 64-bit general path forced
+on 1024^3.
 Taylor-Green initial state on the device; after one (even) and two (even +
 odd) AA steps, sampled cells (corners and the highest linear indices
 included) are compared with the FP64 oracle run on a 9^3 periodic window cut
@@ -45,8 +45,10 @@ def oracle_cell(shape, k, xyz, steps):
     return g.get_pops()[:, HALF, HALF, HALF]
 
 
-@pytest.mark.parametrize("shape", [(1024, 1024, 1016), (1024, 1024, 1024)], ids=["fast-near-limit", "general-64bit"])
-def test_largest_planes_match_oracle(shape):
+@pytest.mark.parametrize("shape,general", [((1024, 1024, 1016), False), ((1024, 1024, 1024), False),
+                                           ((1024, 1024, 1024), True)],
+                         ids=["fast-1016", "fast-1024", "general-1024"])
+def test_largest_planes_match_oracle(shape, general):
     _need_gpu()
     import torch
     from paper_2402_13171_amd.lbm import Lbm
@@ -60,7 +62,7 @@ def test_largest_planes_match_oracle(shape):
     cells = np.vstack([pts, corners])
     lin = cells[:, 0] + nx * (cells[:, 1] + ny * cells[:, 2])
     assert lin.max() == n - 1
-    sim = Lbm(nx, ny, nz, omega=1.9, storage="f32")
+    sim = Lbm(nx, ny, nz, omega=1.9, storage="f32", general_path=general)
     try:
         sim.init_tgv(u0=U0, k=k)
         got = {}
