@@ -102,15 +102,8 @@ __device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned total) {
 // A copy of g whose store base the compiler cannot see through (an empty
 // asm that claims to rewrite the scalar register pair), so that addresses
 // built from it are recomputed rather than kept live.
-__device__ __forceinline__ Geo with_opaque_stride(const Geo &g) {
-    Geo r = g;
-    void *p = r.pops;
-    asm volatile("" : "+s"(p));
-    r.pops = p;
-    return r;
-}
-
 __device__ __forceinline__ void opaque_v(uint32_t &v) { asm volatile("" : "+v"(v)); }
+__device__ __forceinline__ void opaque_s(int &v) { asm volatile("" : "+s"(v)); }
 
 // Odd-step sources outside the box in x for a cell off the z walls (z wraps
 // if periodic): x = -1 gives the inlet equilibrium, x = nx the ghost plane.
@@ -233,17 +226,20 @@ __device__ __forceinline__ void cell_update(const Geo &g, const Physics &ph, int
     else collide_unit_rates(m, om1, ph.omega2, Fx, Fy, Fz, o);
     if (CL == CL_MLP && !valid) return;
     sr_round_cell<T>(o, (uint32_t)cell, ph.sr_seed);
-    // the closure variant needs scalar registers for the network: an opaque
-    // copy of the store base makes the compiler rebuild the z-plane bases of
-    // the stores here instead of holding them from the loads on, and the
-    // offsets are rebuilt from x, y, z rather than held through the network
-    const Geo gw = CL == CL_MLP ? with_opaque_stride(g) : g;
+    // the closure variant needs its registers for the network: the store
+    // offsets and z-plane bases are rebuilt here from opaque copies of x, y
+    // and z instead of being held from the loads on through the network (the
+    // store base itself stays the kernel argument, so the stores keep the
+    // global scalar-base form)
     if (CL == CL_MLP && !BCG) {
         uint32_t xo = (uint32_t)x, yo = (uint32_t)y;
+        int zo = z;
         opaque_v(xo);
         opaque_v(yo);
-        fast_nbr(g, (int)xo, (int)yo, z, n);
+        opaque_s(zo);
+        fast_nbr(g, (int)xo, (int)yo, zo, n);
     }
+    const Geo &gw = g;
 
     if (PAR == 0) {
         if (BCG) Unroll<T, 0>::write_swap_local(g, slot_idx(g, 0, x, y, z), o);

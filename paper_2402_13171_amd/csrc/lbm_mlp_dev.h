@@ -1,18 +1,26 @@
 // Learned eddy-viscosity closure on the matrix cores (gfx950).
 //
 // A wave of 64 cells evaluates the per-cell network 6 -> 32 -> 32 -> 1 with
-// v_mfma_f32_32x32x8_bf16 (32x32 output tile, K = 8, bfloat16 inputs, FP32
-// accumulation), one half-wave of 32 cells per tile:
-//   layer 1: H1 = W1 (32 x 8) * X (8 x 32 cells), features padded 6 -> 8;
-//   layer 2: H2 = W2 (32 x 32) * relu(H1) (32 x 32 cells), 4 K-blocks;
+// gfx950's v_mfma_f32_32x32x16_bf16 (32x32 output tile, K = 16, bfloat16
+// inputs, FP32 accumulation), one half-wave of 32 cells per output tile:
+//   layer 1: H1 = [W1 | 0] or [0 | W1] (32 x 16) * X (16 x 32), where column
+//            c of X holds the features of cells c and c + 32 (6 each, padded
+//            to 8): the zero block picks the half-wave, and every lane passes
+//            its own features, unshuffled;
+//   layer 2: H2 = W2 (32 x 32) * relu(H1) (32 x 32 cells), 2 K-blocks;
 //   layer 3: z = w3 . relu(H2) + b3 on the vector ALU, softplus output.
-// Operand layout of the 32x32x8 instruction (lane l of 64):
-//   A (M x K): row l % 32, k = 4 (l / 32) + j, j = 0..3
-//   B (K x N): col l % 32, k = 4 (l / 32) + j
+// Operand layout of the 32x32x16 instruction (lane l of 64):
+//   A (M x K): row l % 32, k = 8 (l / 32) + j, j = 0..7
+//   B (K x N): col l % 32, k = 8 (l / 32) + j
 //   D (M x N): register r holds row 8 (r / 4) + 4 (l / 32) + r % 4, col l % 32
-// so the D registers 4s..4s+3 of layer 1 are exactly the B operand of K-block
-// s of layer 2: the hidden layer never leaves registers. Feature vectors of
-// one cell per lane reach the B layout of layer 1 with one cross-half swap.
+// The D registers 8s..8s+7 of layer 1 serve as the B operand of K-block s of
+// layer 2 as they are: the hidden layer never leaves registers, and the A
+// operand of that block takes the matching columns of W2 (hidden units
+// 16s + 4 (l / 32) + 0..3 and 16s + 8 + 4 (l / 32) + 0..3); a sum over k does
+// not depend on the order of its terms.
+// The training kernels evaluate the same network with the K = 8 instruction
+// (v_mfma_f32_32x32x8_bf16, A/B lane l: k = 4 (l / 32) + j, j = 0..3) and
+// the same D layout.
 #pragma once
 #include <cstddef>
 #include "lbm_device.h"
@@ -21,6 +29,7 @@
 namespace lbm {
 
 typedef short bf16x4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x16_t __attribute__((ext_vector_type(16)));
 
 __device__ __forceinline__ short bf16s(float v) { return (short)f32_to_bf16_bits(v); }
@@ -122,10 +131,12 @@ __device__ __forceinline__ void mlp_stage_wait() {
 }
 
 // The network operands one lane needs, read once per wave from LDS and shared
-// by both half-wave evaluations: its row of W1 and W2 (A operands) and the 16
-// bias / output-weight entries of the D-register rows it holds.
+// by both half-wave evaluations: its row of W1 in the half of K that selects
+// each half-wave (zero in the other), its columns of W2 for the two K-blocks
+// of layer 2, and the 16 bias / output-weight entries of the D-register rows
+// it holds.
 struct MlpLane {
-    bf16x4_t w1, w2[4];
+    bf16x8_t w1a, w1b, w2[2];
     f32x16_t b1, b2, w3;
 };
 
@@ -142,15 +153,24 @@ __device__ __forceinline__ f32x16_t load_drows(const float *v, int hi) {
     return r;
 }
 
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ bf16x8_t as_bf16x8(uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
+    const u32x4_t v = {a, b, c, d};
+    return __builtin_bit_cast(bf16x8_t, v);
+}
+
 __device__ __forceinline__ MlpLane mlp_lane(const MlpLds &S, int lane) {
     const int row = lane & 31, hi = lane >> 5;
     MlpLane L;
-    const uint2 w = *(const uint2 *)(S.W1 + row * 8 + 4 * hi);
-    L.w1 = as_bf16x4(w.x, w.y);
+    const uint4 w = *(const uint4 *)(S.W1 + row * 8);
+    const bf16x8_t w1 = as_bf16x8(w.x, w.y, w.z, w.w), zero = as_bf16x8(0u, 0u, 0u, 0u);
+    L.w1a = hi ? zero : w1;  // half-wave 0: cells 0..31 are k = 0..7
+    L.w1b = hi ? w1 : zero;  // half-wave 1: cells 32..63 are k = 8..15
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-        const uint2 v = *(const uint2 *)(S.W2 + row * 32 + 8 * s + 4 * hi);
-        L.w2[s] = as_bf16x4(v.x, v.y);
+    for (int s = 0; s < 2; ++s) {
+        const uint2 u = *(const uint2 *)(S.W2 + row * 32 + 16 * s + 4 * hi);
+        const uint2 v = *(const uint2 *)(S.W2 + row * 32 + 16 * s + 8 + 4 * hi);
+        L.w2[s] = as_bf16x8(u.x, u.y, v.x, v.y);
     }
     L.b1 = load_drows(S.b1, hi);
     L.b2 = load_drows(S.b2, hi);
@@ -167,34 +187,33 @@ __device__ __forceinline__ uint32_t relu_bf16x2(uint32_t v) {
     return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(s16x2_t, v), z));
 }
 
-// relu(H1) in bfloat16 from the layer-1 accumulator: registers 4s..4s+3
+// relu(H1) in bfloat16 from the layer-1 accumulator: registers 8s..8s+7
 // form the B operand of K-block s of layer 2
-__device__ __forceinline__ void hidden_bf16(const f32x16_t &acc, bf16x4_t h[4]) {
+__device__ __forceinline__ void hidden_bf16(const f32x16_t &acc, bf16x8_t h[2]) {
 #pragma unroll
-    for (int s = 0; s < 4; ++s)
-        h[s] = as_bf16x4(relu_bf16x2(f32x2_to_bf16x2_bits(acc[4 * s], acc[4 * s + 1])),
-                         relu_bf16x2(f32x2_to_bf16x2_bits(acc[4 * s + 2], acc[4 * s + 3])));
+    for (int s = 0; s < 2; ++s)
+        h[s] = as_bf16x8(relu_bf16x2(f32x2_to_bf16x2_bits(acc[8 * s], acc[8 * s + 1])),
+                         relu_bf16x2(f32x2_to_bf16x2_bits(acc[8 * s + 2], acc[8 * s + 3])),
+                         relu_bf16x2(f32x2_to_bf16x2_bits(acc[8 * s + 4], acc[8 * s + 5])),
+                         relu_bf16x2(f32x2_to_bf16x2_bits(acc[8 * s + 6], acc[8 * s + 7])));
 }
 
 // Both half-wave evaluations, interleaved so that the dependent matrix-core
-// chains of one half overlap the other's. x0 / x1: B operands of layer 1 for
-// the cells of half 0 / 1. Returns z - b3 for the cell in column lane % 32
-// of each half (valid in both lane halves).
-__device__ __forceinline__ void mlp_halves(const MlpLane &L, bf16x4_t x0, bf16x4_t x1, float &z0, float &z1) {
+// chains of one half overlap the other's. x: the B operand of layer 1 (each
+// lane's own features). Returns z - b3 for the cell in column lane % 32 of
+// each half (valid in both lane halves).
+__device__ __forceinline__ void mlp_halves(const MlpLane &L, bf16x8_t x, float &z0, float &z1) {
     // layer 1 (bias as the accumulator input)
-    f32x16_t a0 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(L.w1, x0, L.b1, 0, 0, 0);
-    f32x16_t a1 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(L.w1, x1, L.b1, 0, 0, 0);
-    bf16x4_t h0[4], h1[4];
+    f32x16_t a0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(L.w1a, x, L.b1, 0, 0, 0);
+    f32x16_t a1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(L.w1b, x, L.b1, 0, 0, 0);
+    bf16x8_t h0[2], h1[2];
     hidden_bf16(a0, h0);
     hidden_bf16(a1, h1);
     // layer 2
-    a0 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(L.w2[0], h0[0], L.b2, 0, 0, 0);
-    a1 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(L.w2[0], h1[0], L.b2, 0, 0, 0);
-#pragma unroll
-    for (int s = 1; s < 4; ++s) {
-        a0 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(L.w2[s], h0[s], a0, 0, 0, 0);
-        a1 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(L.w2[s], h1[s], a1, 0, 0, 0);
-    }
+    a0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(L.w2[0], h0[0], L.b2, 0, 0, 0);
+    a1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(L.w2[0], h1[0], L.b2, 0, 0, 0);
+    a0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(L.w2[1], h0[1], a0, 0, 0, 0);
+    a1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(L.w2[1], h1[1], a1, 0, 0, 0);
     // layer 3: this lane holds 16 of the 32 hidden units of its column
     float s0 = 0.0f, s1 = 0.0f;
 #pragma unroll
@@ -213,18 +232,9 @@ __device__ __forceinline__ float mlp_nu_t_wave(const MlpDev &M, const MlpLds &S,
     const int lane = (int)__lane_id();
     uint32_t p[4];
     pack_features(M, f, p);
-    // lanes < 32 need their own features 0..3 for half 0 and the partner's
-    // 0..3 for half 1; lanes >= 32 the partner's 4..7 for half 0 and their
-    // own 4..7 for half 1: send what the partner lacks
-    const uint32_t s0 = lane < 32 ? p[2] : p[0];
-    const uint32_t s1 = lane < 32 ? p[3] : p[1];
-    const uint32_t r0 = (uint32_t)__shfl_xor((int)s0, 32);
-    const uint32_t r1 = (uint32_t)__shfl_xor((int)s1, 32);
-    const bf16x4_t x0 = lane < 32 ? as_bf16x4(p[0], p[1]) : as_bf16x4(r0, r1);
-    const bf16x4_t x1 = lane < 32 ? as_bf16x4(r0, r1) : as_bf16x4(p[2], p[3]);
     const MlpLane L = mlp_lane(S, lane);
     float z0, z1;
-    mlp_halves(L, x0, x1, z0, z1);
+    mlp_halves(L, as_bf16x8(p[0], p[1], p[2], p[3]), z0, z1);
     const float z = (lane < 32 ? z0 : z1) + M.b3;
     return M.nu_scale * softplusf(z);
 }
