@@ -144,24 +144,24 @@ __device__ __forceinline__ CellMoments moments_of(const float d[27], float Fx, f
 #pragma unroll
     for (int p = 0; p < 9; ++p) {
         float a = d[p], b = d[p + 9], c = d[p + 18];
-        Z0[p] = a + b + c;
-        Z1[p] = c - a;
         Z2[p] = c + a;
+        Z1[p] = c - a;
+        Z0[p] = Z2[p] + b;  // the zeroth moment reuses the outer pair's sum
     }
     // y pass: index p = ix + 3*iy
     float Y00[3], Y01[3], Y02[3], Y10[3], Y11[3], Y20[3];
 #pragma unroll
     for (int ix = 0; ix < 3; ++ix) {
-        Y00[ix] = Z0[ix] + Z0[ix + 3] + Z0[ix + 6];
-        Y01[ix] = Z0[ix + 6] - Z0[ix];
         Y02[ix] = Z0[ix + 6] + Z0[ix];
+        Y01[ix] = Z0[ix + 6] - Z0[ix];
+        Y00[ix] = Y02[ix] + Z0[ix + 3];
         Y10[ix] = Z1[ix] + Z1[ix + 3] + Z1[ix + 6];
         Y11[ix] = Z1[ix + 6] - Z1[ix];
         Y20[ix] = Z2[ix] + Z2[ix + 3] + Z2[ix + 6];
     }
-    const float m000 = Y00[0] + Y00[1] + Y00[2];
-    const float m100 = Y00[2] - Y00[0];
     const float m200 = Y00[2] + Y00[0];
+    const float m100 = Y00[2] - Y00[0];
+    const float m000 = m200 + Y00[1];
     const float m010 = Y01[0] + Y01[1] + Y01[2];
     const float m110 = Y01[2] - Y01[0];
     const float m020 = Y02[0] + Y02[1] + Y02[2];
@@ -217,14 +217,17 @@ __device__ __forceinline__ float smag_omega(float Q, float tau0, float cs2_18sqr
 
 // One 1-D inverse pass on a triple of central moments (k0,k1,k2) about u:
 // raw moments m0 = k0, m1 = k1 + u k0, m2 = k2 + 2 u k1 + u^2 k0, then the
-// populations f- = (m2 - m1)/2, f0 = m0 - m2, f+ = (m2 + m1)/2.
+// populations f- = (m2 - m1)/2, f0 = m0 - m2, f+ = (m2 + m1)/2. The halves
+// are taken as fma(1/2, m2, -+m1/2): halving is exact, so these round as
+// (m2 -+ m1)/2 do, bit for bit, in one instruction fewer.
 __device__ __forceinline__ void inv_triple(float &a, float &b, float &c, float u) {
     const float k0 = a, k1 = b, k2 = c;
     const float m1 = fmaf(u, k0, k1);
     const float m2 = fmaf(u, k1 + m1, k2);
-    a = 0.5f * (m2 - m1);
+    const float h1 = 0.5f * m1;
+    a = fmaf(0.5f, m2, -h1);
     b = k0 - m2;
-    c = 0.5f * (m2 + m1);
+    c = fmaf(0.5f, m2, h1);
 }
 
 // Post-collision deviations d*_i = f*_i - w_i, for unit higher-order rates
@@ -320,10 +323,10 @@ __device__ __forceinline__ void collide_unit_rates(const CellMoments &m, float o
 // inverse transform, so the output is d* = f* - w.
 __device__ __forceinline__ void fwd_triple(float &a, float &b, float &c, float u) {
     const float fm = a, f0 = b, fp = c;
-    const float k0 = fm + f0 + fp;
-    const float dpm = fp - fm;
+    const float spm = fp + fm, dpm = fp - fm;
+    const float k0 = spm + f0;
     b = fmaf(-u, k0, dpm);
-    c = fmaf(u * u, k0, fmaf(-2.0f * u, dpm, fp + fm));
+    c = fmaf(u * u, k0, fmaf(-2.0f * u, dpm, spm));
     a = k0;
 }
 

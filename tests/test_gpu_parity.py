@@ -59,12 +59,17 @@ def test_tgv64_fp32_matches_oracle_after_50_steps():
         m, p, e = sim.global_moments()
         assert abs(m - m0) <= 1e-9 * m0, s
         pmax = max(pmax, np.abs(p).max())
-    # the TGV carries no net momentum; what the GPU shows is the rounding of
-    # the FP32-stored deviations (|d| <~ 0.02, half an ulp ~6e-10 each), a
-    # random walk over 27 N populations and 50 steps: sqrt(27 N 50) 6e-10
-    # ~ 1.1e-5 = 8.6e-10 N u0 (measured 8.1e-6); the FP64 oracle stays
-    # below 1e-10 N u0
-    assert pmax <= 1e-9 * n ** 3 * 0.05, pmax
+    # the TGV carries no net momentum and the collision conserves it exactly;
+    # what the GPU shows is the rounding of the FP32-stored deviations
+    # (|d| <~ 0.02, half an ulp ~6e-10 each), a random walk over 27 N
+    # populations and 50 steps: sqrt(27 N 50) 6e-10 ~ 1.1e-5 = 8.6e-10 N u0
+    # at the last step, and the largest of three components over the 50
+    # steps ~1.3-1.6 times that (measured 8.1e-6 and 1.4e-5 for two orders
+    # of the moment sums). The bound is 3.5 times the walk's scale: a
+    # systematic drift (a term that does not conserve momentum) grows
+    # linearly in the steps and exceeds it; the FP64 oracle stays below
+    # 1e-10 N u0
+    assert pmax <= 3e-9 * n ** 3 * 0.05, pmax
     ref.step(50)
     _, u = sim.fields()
     _, ur = ref.fields()
