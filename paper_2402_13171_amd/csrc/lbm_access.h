@@ -265,10 +265,30 @@ struct Unroll32<T, 27> {
 };
 
 // ------------------------------------------------------------ readers
+// A swapped-layout read of cell (x, y, z) needs no boundary rule when none of
+// its 26 neighbours lies across an open x face or a z wall; it is then the
+// fast path's periodic-wrap read (valid while a z plane of blocks has fewer
+// than 2^32 bytes), whose 27 loads are independent of each other.
+template <typename T>
+__device__ __forceinline__ bool swapped_read_is_plain(const Geo &g, int x, int z) {
+    const bool fits = (size_t)g.ny * (size_t)g.nbx * BLK_SLOTS * sizeof(T) < ((size_t)1 << 32);
+    const bool xin = g.bc_x == BC_PERIODIC || (x > 0 && x < g.nx - 1);
+    const bool zlo = g.bc_zlo == BC_NOSLIP || g.bc_zlo == BC_FREESLIP;
+    const bool zhi = g.bc_zhi == BC_NOSLIP || g.bc_zhi == BC_FREESLIP;
+    return fits && xin && (!zlo || z > 0) && (!zhi || z < g.nz - 1);
+}
+
 template <typename T, int PAR>
 __device__ __forceinline__ void read_cell(const Geo &g, size_t cell, int x, int y, int z, float *d) {
-    if (PAR == 0) Unroll<T, 0>::read_natural(g, slot_idx(g, 0, x, y, z), d);
-    else Unroll<T, 0>::read_sw(g, x, y, z, d);
+    if (PAR == 0) {
+        Unroll<T, 0>::read_natural(g, slot_idx(g, 0, x, y, z), d);
+    } else if (swapped_read_is_plain<T>(g, x, z)) {
+        Nbr n;
+        fast_nbr(g, x, y, z, n);
+        Unroll32<T, 0>::read_periodic(g, n, d);
+    } else {
+        Unroll<T, 0>::read_sw(g, x, y, z, d);
+    }
 }
 
 // rho, j (FP64 sums of the stored deviations) and u with half the force

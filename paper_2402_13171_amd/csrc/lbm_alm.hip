@@ -11,7 +11,7 @@
 namespace lbm {
 
 constexpr int ALM_BLOCK = 256;
-constexpr int ALM_MAX_PTS = 512;
+constexpr int ALM_MAX_PTS = ALM_MAX_POINTS;  // points per slot (checked on the host)
 constexpr double PI_D = 3.14159265358979323846;
 
 __device__ __forceinline__ double polar_lookup(double a, const RotorDev &R, const float *tab) {
@@ -144,14 +144,14 @@ __device__ __forceinline__ void slot_point(const RotorDev &R, const TreePose *po
 
 // Blade-element force (Sec. 2.2) from the in-plane relative wind: W_n along
 // the rotor normal, W_t against the blade's motion; Fn, Ft along e_n, e_t.
-__device__ __forceinline__ void blade_element(const RotorDev &R, double rho, double wn, double wt, double chord,
-                                              double dl, double twist, double pitch, int tip_loss, double r,
-                                              double &Fn, double &Ft) {
+__device__ __forceinline__ void blade_element(const RotorDev &R, const float *cl, const float *cd, double rho,
+                                              double wn, double wt, double chord, double dl, double twist,
+                                              double pitch, int tip_loss, double r, double &Fn, double &Ft) {
     double a = atan2(wn, wt) * (180.0 / PI_D) - twist - pitch;
     // |phi| <= 180 and |twist + pitch| < 180: one correction wraps to [-180, 180)
     if (a >= 180.0) a -= 360.0;
     else if (a < -180.0) a += 360.0;
-    const double CL = polar_lookup(a, R, R.cl), CD = polar_lookup(a, R, R.cd);
+    const double CL = polar_lookup(a, R, cl), CD = polar_lookup(a, R, cd);
     const double w2 = wn * wn + wt * wt, wm = sqrt(w2);
     const double q = 0.5 * rho * w2 * chord * dl;
     Fn = 0.0;
@@ -229,6 +229,7 @@ __global__ __launch_bounds__(ALM_BLOCK) void k_alm_points(Geo g, Physics ph, Rot
     }
     __syncthreads();
     if (threadIdx.x < ALM_BATCH) {
+        const float *pcl = R.cl, *pcd = R.cd;
         double accT = 0.0, accQ = 0.0;
         const int p = base + threadIdx.x;
         if (p < npts) {
@@ -256,7 +257,8 @@ __global__ __launch_bounds__(ALM_BLOCK) void k_alm_points(Geo g, Physics ph, Rot
                 const double wn = sm[1];
                 const double wt = -(ut - R.omega_rot * rr);
                 double Fn, Ft;
-                blade_element(R, rho, wn, wt, pre_chord, pre_dl, pre_twist, R.pitch_deg, R.tip_loss, rr, Fn, Ft);
+                blade_element(R, pcl, pcd, rho, wn, wt, pre_chord, pre_dl, pre_twist, R.pitch_deg, R.tip_loss, rr, Fn,
+                              Ft);
                 Fp[0] = Fn;
                 Fp[1] = -Ft * st;
                 Fp[2] = Ft * ct;
@@ -273,8 +275,8 @@ __global__ __launch_bounds__(ALM_BLOCK) void k_alm_points(Geo g, Physics ph, Rot
                     cross3(en, es, et);
                     const double wn = dot3(W, en), wt = -dot3(W, et);
                     double Fn, Ft;
-                    blade_element(R, rho, wn, wt, tp.chord, tp.measure, tp.twist, N.pitch_deg, N.tip_loss, tp.s, Fn,
-                                  Ft);
+                    blade_element(R, pcl, pcd, rho, wn, wt, tp.chord, tp.measure, tp.twist, N.pitch_deg, N.tip_loss,
+                                  tp.s, Fn, Ft);
                     for (int a = 0; a < 3; ++a) Fp[a] = Fn * en[a] + Ft * et[a];
                 } else if (N.force == LBM_FORCE_DRAG && N.kind == LBM_NODE_LINE) {
                     // cross-flow drag of a cylinder: the part of W normal to the line
@@ -360,11 +362,14 @@ __global__ __launch_bounds__(ALM_BLOCK) void k_alm_spread(const RotorDev *rots, 
     const int npts = R.npts;
     const ForceBox &B = R.box;
     const int half = R.half, W = 2 * half + 1;  // half <= SUPPORT (checked on the host)
-    __shared__ int s_idx[ALM_MAX_PTS];
+    // the kept points' records, in point order: offset from the nearest node,
+    // -F and (per chunk) 1 / W_p, the nearest node
+    __shared__ float s_off[ALM_MAX_PTS][3];
+    __shared__ float s_f[ALM_MAX_PTS][4];
+    __shared__ int s_c[ALM_MAX_PTS][3];
     __shared__ int s_wave[ALM_BLOCK / 64];
-    __shared__ float s_g[SP_CHUNK][3][SP_W];  // per-axis factors of the kept points
-    __shared__ float s_f[SP_CHUNK][4];        // -F_p and 1 / W_p
-    __shared__ int s_c[SP_CHUNK][3];          // nearest node of the point
+    __shared__ float s_g[SP_CHUNK][3][SP_W];  // per-axis factors of a chunk of kept points
+    __shared__ float s_sum[SP_CHUNK][3];      // and their sums over the support
     const int tx = blk % tiles_x, ty = (blk / tiles_x) % tiles_y, tz = blk / (tiles_x * tiles_y);
     // tile extent in lattice coordinates (clipped to the box)
     const int X0 = B.x0 + tx * SP_TX, Y0 = B.y0 + ty * SP_TY, Z0 = B.z0 + tz * SP_TZ;
@@ -375,9 +380,13 @@ __global__ __launch_bounds__(ALM_BLOCK) void k_alm_spread(const RotorDev *rots, 
     for (int k0 = 0; k0 < npts; k0 += ALM_BLOCK) {
         const int p = k0 + threadIdx.x;
         bool reach = false;
+        float rec[9];
         if (p < npts) {
+            // the whole record in one round trip, kept in LDS if the point reaches the tile
             const float *P = R.pts + (size_t)p * PT_STRIDE;
-            const int cx = (int)P[6], cy = (int)P[7], cz = (int)P[8];
+#pragma unroll
+            for (int q = 0; q < 9; ++q) rec[q] = P[q];
+            const int cx = (int)rec[6], cy = (int)rec[7], cz = (int)rec[8];
             reach = cx - half <= X1 && cx + half >= X0 && cy - half <= Y1 && cy + half >= Y0 && cz - half <= Z1 &&
                     cz + half >= Z0;
         }
@@ -386,7 +395,15 @@ __global__ __launch_bounds__(ALM_BLOCK) void k_alm_spread(const RotorDev *rots, 
         __syncthreads();
         int off = count;
         for (int w = 0; w < wave; ++w) off += s_wave[w];
-        if (reach) s_idx[off + __popcll(bal & ((1ull << lane) - 1ull))] = p;
+        if (reach) {
+            const int k = off + __popcll(bal & ((1ull << lane) - 1ull));
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                s_off[k][a] = rec[a];
+                s_f[k][a] = rec[3 + a];
+                s_c[k][a] = (int)rec[6 + a];
+            }
+        }
         for (int w = 0; w < ALM_BLOCK / 64; ++w) count += s_wave[w];
         __syncthreads();
     }
@@ -398,42 +415,37 @@ __global__ __launch_bounds__(ALM_BLOCK) void k_alm_spread(const RotorDev *rots, 
     float Fx = 0.f, Fy = 0.f, Fz = 0.f;
     for (int c0 = 0; c0 < count; c0 += SP_CHUNK) {
         const int nk = min(SP_CHUNK, count - c0);
-        // factors: e = d - (x_p - node) for d = -half..half on each axis
-        for (int q = threadIdx.x; q < nk * 3 * W; q += ALM_BLOCK) {
-            const int k = q / (3 * W), ax = (q / W) % 3, d = q % W - half;
-            const float e = (float)d - R.pts[(size_t)s_idx[c0 + k] * PT_STRIDE + ax];
-            s_g[k][ax][d + half] = roma ? roma_phi(e) : expf(-e * e * ie2);
-        }
-        for (int q = threadIdx.x; q < nk; q += ALM_BLOCK) {
-            const float *P = R.pts + (size_t)s_idx[c0 + q] * PT_STRIDE;
-            s_f[q][0] = P[3];
-            s_f[q][1] = P[4];
-            s_f[q][2] = P[5];
-            s_c[q][0] = (int)P[6];
-            s_c[q][1] = (int)P[7];
-            s_c[q][2] = (int)P[8];
+        // factors: e = d - (x_p - node) for d = -half..half on each axis, one
+        // thread per (point, axis), which also sums its row
+        for (int q = threadIdx.x; q < nk * 3; q += ALM_BLOCK) {
+            const int k = q / 3, ax = q % 3;
+            const float o = s_off[c0 + k][ax];
+            float sa = 0.0f;
+            for (int d = 0; d < W; ++d) {
+                const float e = (float)(d - half) - o;
+                const float v = roma ? roma_phi(e) : expf(-e * e * ie2);
+                s_g[k][ax][d] = v;
+                sa += v;
+            }
+            s_sum[k][ax] = sa;
         }
         __syncthreads();
         for (int q = threadIdx.x; q < nk; q += ALM_BLOCK) {
             double S = 1.0;
-            if (!roma) {
-                for (int ax = 0; ax < 3; ++ax) {
-                    float sa = 0.0f;
-                    for (int d = 0; d < W; ++d) sa += s_g[q][ax][d];
-                    S *= (double)sa;
-                }
-            }
-            s_f[q][3] = (float)(1.0 / S);
+            if (!roma)
+                for (int ax = 0; ax < 3; ++ax) S *= (double)s_sum[q][ax];
+            s_f[c0 + q][3] = (float)(1.0 / S);
         }
         __syncthreads();
         if (mine) {
             for (int k = 0; k < nk; ++k) {
-                const int dx = X - s_c[k][0] + half, dy = Y - s_c[k][1] + half, dz = Z - s_c[k][2] + half;
+                const int j = c0 + k;
+                const int dx = X - s_c[j][0] + half, dy = Y - s_c[j][1] + half, dz = Z - s_c[j][2] + half;
                 if ((unsigned)dx >= (unsigned)W || (unsigned)dy >= (unsigned)W || (unsigned)dz >= (unsigned)W) continue;
-                const float w = s_g[k][0][dx] * s_g[k][1][dy] * s_g[k][2][dz] * s_f[k][3];
-                Fx = fmaf(w, s_f[k][0], Fx);
-                Fy = fmaf(w, s_f[k][1], Fy);
-                Fz = fmaf(w, s_f[k][2], Fz);
+                const float w = s_g[k][0][dx] * s_g[k][1][dy] * s_g[k][2][dz] * s_f[j][3];
+                Fx = fmaf(w, s_f[j][0], Fx);
+                Fy = fmaf(w, s_f[j][1], Fy);
+                Fz = fmaf(w, s_f[j][2], Fz);
             }
         }
         __syncthreads();  // the next chunk overwrites the tables
