@@ -14,14 +14,21 @@ constexpr int ALM_BLOCK = 256;
 constexpr int ALM_MAX_PTS = ALM_MAX_POINTS;  // points per slot (checked on the host)
 constexpr double PI_D = 3.14159265358979323846;
 
-__device__ __forceinline__ double polar_lookup(double a, const RotorDev &R, const float *tab) {
-    const double s = (a - R.alpha0) / R.dalpha;
-    if (!(s > 0.0)) return tab[0];  // also catches NaN: the index below stays in range
-    if (s >= R.n_polar - 1) return tab[R.n_polar - 1];
-    int k = (int)floor(s);
-    if (k > R.n_polar - 2) k = R.n_polar - 2;
-    const double t = s - k;
-    return (double)tab[k] * (1.0 - t) + (double)tab[k + 1] * t;
+// Lift and drag by linear interpolation in the polar tables on the uniform
+// grid alpha0 + k dalpha (degrees), clamped to their ends (s <= 0 or NaN: the
+// first entry, s >= n - 1: the last one, both exactly); FP32, like the
+// tables. One index for both tables and no branch, so that the four loads
+// are in flight together.
+__device__ __forceinline__ void polar_pair(float a, const RotorDev &R, const float *cl, const float *cd, float &CL,
+                                           float &CD) {
+    const float last = (float)(R.n_polar - 1);
+    float s = (a - R.alpha0_f) * R.inv_dalpha_f;
+    s = s > 0.0f ? fminf(s, last) : 0.0f;
+    const int k = min((int)floorf(s), R.n_polar - 2);
+    const float t = fminf(s - (float)k, 1.0f);
+    const float l0 = cl[k], l1 = cl[k + 1], d0 = cd[k], d1 = cd[k + 1];
+    CL = l0 * (1.0f - t) + l1 * t;
+    CD = d0 * (1.0f - t) + d1 * t;
 }
 
 __device__ __forceinline__ int wrap_any(int v, int n) { return ((v % n) + n) % n; }
@@ -40,11 +47,11 @@ __device__ __forceinline__ float roma_phi(float r) {
 
 // Prandtl tip-loss factor 2/pi arccos(exp(-f)), f = B (R - r) / (2 r |sin phi|):
 // zero at and beyond the tip, one for wind in the rotor plane.
-__device__ __forceinline__ double tip_loss_factor(int B, double R, double r, double phi) {
-    if (!(r < R)) return 0.0;
-    const double s = fabs(sin(phi));
-    if (s == 0.0) return 1.0;
-    return (2.0 / PI_D) * acos(exp(-0.5 * B * (R - r) / (r * s)));
+__device__ __forceinline__ float tip_loss_factor(int B, float R, float r, float phi) {
+    if (!(r < R)) return 0.0f;
+    const float s = fabsf(sinf(phi));
+    if (s == 0.0f) return 1.0f;
+    return (float)(2.0 / PI_D) * acosf(expf(-0.5f * (float)B * (R - r) / (r * s)));
 }
 
 // ------------------------------------------------------------ turbine tree
@@ -144,27 +151,33 @@ __device__ __forceinline__ void slot_point(const RotorDev &R, const TreePose *po
 
 // Blade-element force (Sec. 2.2) from the in-plane relative wind: W_n along
 // the rotor normal, W_t against the blade's motion; Fn, Ft along e_n, e_t.
-__device__ __forceinline__ void blade_element(const RotorDev &R, const float *cl, const float *cd, double rho,
-                                              double wn, double wt, double chord, double dl, double twist,
-                                              double pitch, int tip_loss, double r, double &Fn, double &Ft) {
-    double a = atan2(wn, wt) * (180.0 / PI_D) - twist - pitch;
+// Evaluated in FP32 (the sampled velocity comes from FP32 or 16-bit
+// populations and the polars are FP32 tables); the load sums stay FP64.
+__device__ __forceinline__ void blade_element(const RotorDev &R, const float *cl, const float *cd, double rho_d,
+                                              double wn_d, double wt_d, double chord, double dl, double twist,
+                                              double pitch, int tip_loss, double r, double &Fn_d, double &Ft_d) {
+    const float rho = (float)rho_d, wn = (float)wn_d, wt = (float)wt_d;
+    const float phi = atan2f(wn, wt);
+    float a = phi * (float)(180.0 / PI_D) - (float)twist - (float)pitch;
     // |phi| <= 180 and |twist + pitch| < 180: one correction wraps to [-180, 180)
-    if (a >= 180.0) a -= 360.0;
-    else if (a < -180.0) a += 360.0;
-    const double CL = polar_lookup(a, R, cl), CD = polar_lookup(a, R, cd);
-    const double w2 = wn * wn + wt * wt, wm = sqrt(w2);
-    const double q = 0.5 * rho * w2 * chord * dl;
-    Fn = 0.0;
-    Ft = 0.0;
-    if (wm > 0.0) {
+    if (a >= 180.0f) a -= 360.0f;
+    else if (a < -180.0f) a += 360.0f;
+    float CL, CD;
+    polar_pair(a, R, cl, cd, CL, CD);
+    const float w2 = wn * wn + wt * wt, wm = sqrtf(w2);
+    const float q = 0.5f * rho * w2 * (float)chord * (float)dl;
+    float Fn = 0.0f, Ft = 0.0f;
+    if (wm > 0.0f) {
         Fn = q * (CL * wt + CD * wn) / wm;
         Ft = q * (CL * wn - CD * wt) / wm;
     }
     if (tip_loss) {
-        const double Fl = tip_loss_factor(R.n_blades, R.radius, r, atan2(wn, wt));
+        const float Fl = tip_loss_factor(R.n_blades, (float)R.radius, (float)r, phi);
         Fn *= Fl;
         Ft *= Fl;
     }
+    Fn_d = Fn;
+    Ft_d = Ft;
 }
 
 // Points are processed in batches of 32: workgroup (b, r) handles points
@@ -179,15 +192,23 @@ constexpr int ALM_BATCH = ALM_BLOCK / 8;
 static_assert(ALM_BATCH == ALM_BATCH_PTS, "batch size shared with the host-side load sum");
 constexpr int ALM_MAX_BATCHES = ALM_MAX_PTS / ALM_BATCH;
 
+struct PointsLds {
+    double corner[ALM_BLOCK][4];     // rho, u of one corner cell per work item
+    TreePose pose[TREE_MAX_NODES];   // turbine: every node's pose at this step
+    NodeDev nodes[TREE_MAX_NODES];   // turbine: the node table
+};
+
+// batch bx of slot by
 template <typename T, int PAR>
-__global__ __launch_bounds__(ALM_BLOCK) void k_alm_points(Geo g, Physics ph, RotorDev *rots, long t) {
-    RotorDev &R = rots[blockIdx.y];
+__device__ __forceinline__ void alm_points_wg(const Geo &g, const Physics &ph, RotorDev *rots, long t, int bx,
+                                              int by, PointsLds &L) {
+    RotorDev &R = rots[by];
     const int npts = R.npts;
-    const int base = blockIdx.x * ALM_BATCH;
+    const int base = bx * ALM_BATCH;
     if (base >= npts) return;  // uniform across the workgroup
-    __shared__ double s_corner[ALM_BLOCK][4];  // rho, u of one corner cell per work item
-    __shared__ TreePose s_pose[TREE_MAX_NODES];  // turbine: every node's pose at this step
-    __shared__ NodeDev s_nodes[TREE_MAX_NODES];  // turbine: the node table
+    double(*s_corner)[4] = L.corner;
+    TreePose *s_pose = L.pose;
+    NodeDev *s_nodes = L.nodes;
     // the blade data of the batch's points into registers, in flight with
     // the sampling
     double pre_r = 0.0, pre_chord = 0.0, pre_dl = 0.0, pre_twist = 0.0;
@@ -235,7 +256,19 @@ __global__ __launch_bounds__(ALM_BLOCK) void k_alm_points(Geo g, Physics ph, Rot
         if (p < npts) {
             double xp[3], vp[3] = {0, 0, 0}, Tq[3] = {0, 0, 0};
             TreePose P;
-            slot_point(R, s_pose, p, (double)t, xp, vp, &P, Tq);
+            double ct = 0.0, st = 0.0;  // rotor: cos, sin of the blade's azimuth
+            if (!R.nodes) {
+                // slot_point's arithmetic, with the radius loaded at the start
+                const int b = p / R.n_points;
+                const double th = R.azimuth0 + R.omega_rot * (double)t + 2.0 * PI_D * b / R.n_blades;
+                ct = cos(th);
+                st = sin(th);
+                xp[0] = R.hub[0];
+                xp[1] = R.hub[1] + pre_r * ct;
+                xp[2] = R.hub[2] + pre_r * st;
+            } else {
+                slot_point(R, s_pose, p, (double)t, xp, vp, &P, Tq);
+            }
             double fr[3];
             for (int a = 0; a < 3; ++a) fr[a] = xp[a] - floor(xp[a]);
             double sm[4] = {0, 0, 0, 0};
@@ -247,11 +280,7 @@ __global__ __launch_bounds__(ALM_BLOCK) void k_alm_points(Geo g, Physics ph, Rot
             const double rho = sm[0];
             double Fp[3] = {0.0, 0.0, 0.0};
             if (!R.nodes) {
-                const int b = p / R.n_points, k = p % R.n_points;
-                const double th = R.azimuth0 + R.omega_rot * (double)t + 2.0 * PI_D * b / R.n_blades;
-                const double ct = cos(th), st = sin(th);
                 const double rr = pre_r;  // R.r[k], R.chord[k], ... loaded at the start
-                (void)k;
                 // e_theta = (0, -sin, cos); relative in-plane wind W = W_n e_x - W_t e_theta
                 const double ut = -sm[2] * st + sm[3] * ct;
                 const double wn = sm[1];
@@ -322,8 +351,8 @@ __global__ __launch_bounds__(ALM_BLOCK) void k_alm_points(Geo g, Physics ph, Rot
             accQ += __shfl_down(accQ, s);
         }
         if (threadIdx.x == 0) {
-            R.loads[3 + 2 * blockIdx.x] = accT;
-            R.loads[4 + 2 * blockIdx.x] = accQ;
+            R.loads[3 + 2 * bx] = accT;
+            R.loads[4 + 2 * bx] = accQ;
         }
     }
 }
@@ -336,14 +365,26 @@ __global__ __launch_bounds__(ALM_BLOCK) void k_alm_points(Geo g, Physics ph, Rot
 // splits, Roma's delta is defined that way), so the workgroup tabulates, for
 // each kept point, the factor of every support offset on each axis in LDS
 // (Gaussian: W_p, the sum of its weights over the support, is the product of
-// the three table sums; the Roma delta's weights sum to one), and each cell
-// then sums over the kept points with three table reads per point: the same
-// terms in the same order as a sum over every point that skips the ones out
-// of reach, so the result does not depend on the tiling. Points are taken
-// in chunks of SP_CHUNK.
+// the three table sums; the Roma delta's weights sum to one). The y and z
+// factors, 1 / W_p and -F_p are then combined once per (point, (y, z) row of
+// the tile), and each cell sums over the kept points g_x(X) times its row's
+// vector: the same terms, each rounded the same way wherever the tile
+// boundaries fall, in point order, so the result does not depend on the
+// tiling. Points are taken in chunks of SP_CHUNK.
 constexpr int SP_TX = 16, SP_TY = 4, SP_TZ = 4;
 static_assert(SP_TX * SP_TY * SP_TZ == ALM_BLOCK, "one cell per thread");
 constexpr int SP_CHUNK = 64;
+constexpr int SP_UNROLL = 8;
+constexpr int SP_ROWS = SP_TY * SP_TZ;  // (y, z) rows of SP_TX cells in a tile
+// a kept point as the per-cell sum reads it (two 16-byte LDS reads): its
+// nearest node minus the support half-width, 1 / W_p and -F_p
+struct KeptPoint {
+    int c[3];
+    float inv_w;
+    float f[3];
+    float pad;
+};
+static_assert(sizeof(KeptPoint) == 32, "two 16-byte reads");
 constexpr int SP_W = 2 * SUPPORT + 1;  // widest support (Gaussian), offsets -SUPPORT..SUPPORT
 
 // One launch spreads every slot: workgroups [first[r], first[r+1]) take the
@@ -354,22 +395,33 @@ struct SpreadTiles {
     int tx[MAX_ROTORS], ty[MAX_ROTORS];
 };
 
-__global__ __launch_bounds__(ALM_BLOCK) void k_alm_spread(const RotorDev *rots, SpreadTiles st) {
+struct SpreadLds {
+    // the kept points' records, in point order: offset from the nearest node,
+    // the nearest node minus the support half-width, -F and (per chunk) 1 / W_p
+    float off[ALM_MAX_PTS][3];
+    KeptPoint k[ALM_MAX_PTS];
+    int wave[ALM_BLOCK / 64];
+    float g[SP_CHUNK][3][SP_W];      // per-axis factors of a chunk of kept points
+    float sum[SP_CHUNK][3];          // and their sums over the support
+    float4 row[SP_CHUNK][SP_ROWS];   // y, z factors x 1/W_p x (-F_p) per tile row
+};
+
+// the spreading workgroup blk of the launch (over all slots)
+__device__ __forceinline__ void alm_spread_wg(const RotorDev *rots, const SpreadTiles &st, int blk_all,
+                                              SpreadLds &L) {
     int rid = 0;
-    while (rid + 1 < st.nslots && (int)blockIdx.x >= st.first[rid + 1]) ++rid;  // uniform per workgroup
-    const int blk = (int)blockIdx.x - st.first[rid], tiles_x = st.tx[rid], tiles_y = st.ty[rid];
+    while (rid + 1 < st.nslots && blk_all >= st.first[rid + 1]) ++rid;  // uniform per workgroup
+    const int blk = blk_all - st.first[rid], tiles_x = st.tx[rid], tiles_y = st.ty[rid];
     const RotorDev &R = rots[rid];
     const int npts = R.npts;
     const ForceBox &B = R.box;
     const int half = R.half, W = 2 * half + 1;  // half <= SUPPORT (checked on the host)
-    // the kept points' records, in point order: offset from the nearest node,
-    // -F and (per chunk) 1 / W_p, the nearest node
-    __shared__ float s_off[ALM_MAX_PTS][3];
-    __shared__ float s_f[ALM_MAX_PTS][4];
-    __shared__ int s_c[ALM_MAX_PTS][3];
-    __shared__ int s_wave[ALM_BLOCK / 64];
-    __shared__ float s_g[SP_CHUNK][3][SP_W];  // per-axis factors of a chunk of kept points
-    __shared__ float s_sum[SP_CHUNK][3];      // and their sums over the support
+    float(*s_off)[3] = L.off;
+    KeptPoint *s_k = L.k;
+    int *s_wave = L.wave;
+    float(*s_g)[3][SP_W] = L.g;
+    float(*s_sum)[3] = L.sum;
+    float4(*s_row)[SP_ROWS] = L.row;
     const int tx = blk % tiles_x, ty = (blk / tiles_x) % tiles_y, tz = blk / (tiles_x * tiles_y);
     // tile extent in lattice coordinates (clipped to the box)
     const int X0 = B.x0 + tx * SP_TX, Y0 = B.y0 + ty * SP_TY, Z0 = B.z0 + tz * SP_TZ;
@@ -400,8 +452,8 @@ __global__ __launch_bounds__(ALM_BLOCK) void k_alm_spread(const RotorDev *rots, 
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 s_off[k][a] = rec[a];
-                s_f[k][a] = rec[3 + a];
-                s_c[k][a] = (int)rec[6 + a];
+                s_k[k].f[a] = rec[3 + a];
+                s_k[k].c[a] = (int)rec[6 + a] - half;
             }
         }
         for (int w = 0; w < ALM_BLOCK / 64; ++w) count += s_wave[w];
@@ -434,18 +486,44 @@ __global__ __launch_bounds__(ALM_BLOCK) void k_alm_spread(const RotorDev *rots, 
             double S = 1.0;
             if (!roma)
                 for (int ax = 0; ax < 3; ++ax) S *= (double)s_sum[q][ax];
-            s_f[c0 + q][3] = (float)(1.0 / S);
+            s_k[c0 + q].inv_w = (float)(1.0 / S);
+        }
+        __syncthreads();
+        // the y and z factors of each kept point for each (y, z) row of the
+        // tile, times 1 / W_p and -F_p: one float4 per (point, row), with the
+        // point's window start in x (zero where the row is outside its window)
+        for (int q = threadIdx.x; q < nk * SP_ROWS; q += ALM_BLOCK) {
+            const int k = q / SP_ROWS, r = q % SP_ROWS;
+            const KeptPoint &P = s_k[c0 + k];
+            const int dy = Y0 + r % SP_TY - P.c[1], dz = Z0 + r / SP_TY - P.c[2];
+            const bool in = (unsigned)dy < (unsigned)W && (unsigned)dz < (unsigned)W;
+            const float a = in ? s_g[k][1][dy] * s_g[k][2][dz] * P.inv_w : 0.0f;
+            s_row[k][r] = make_float4(a * P.f[0], a * P.f[1], a * P.f[2], __int_as_float(P.c[0]));
         }
         __syncthreads();
         if (mine) {
-            for (int k = 0; k < nk; ++k) {
-                const int j = c0 + k;
-                const int dx = X - s_c[j][0] + half, dy = Y - s_c[j][1] + half, dz = Z - s_c[j][2] + half;
-                if ((unsigned)dx >= (unsigned)W || (unsigned)dy >= (unsigned)W || (unsigned)dz >= (unsigned)W) continue;
-                const float w = s_g[k][0][dx] * s_g[k][1][dy] * s_g[k][2][dz] * s_f[j][3];
-                Fx = fmaf(w, s_f[j][0], Fx);
-                Fy = fmaf(w, s_f[j][1], Fy);
-                Fz = fmaf(w, s_f[j][2], Fz);
+            // per cell: F += g_x(X) A(row); SP_UNROLL points at a time, so that
+            // their LDS reads are in flight together, in point order
+            const int r = (int)threadIdx.x / SP_TX;
+            for (int k0 = 0; k0 < nk; k0 += SP_UNROLL) {
+                float gx[SP_UNROLL];
+                float4 A[SP_UNROLL];
+                bool in[SP_UNROLL];
+#pragma unroll
+                for (int u = 0; u < SP_UNROLL; ++u) {
+                    const int k = k0 + u < nk ? k0 + u : k0;  // past the end: a valid entry, not used
+                    A[u] = s_row[k][r];
+                    const int dx = X - __float_as_int(A[u].w);
+                    in[u] = k0 + u < nk && (unsigned)dx < (unsigned)W;
+                    gx[u] = s_g[k][0][in[u] ? dx : 0];
+                }
+#pragma unroll
+                for (int u = 0; u < SP_UNROLL; ++u)
+                    if (in[u]) {
+                        Fx = fmaf(gx[u], A[u].x, Fx);
+                        Fy = fmaf(gx[u], A[u].y, Fy);
+                        Fz = fmaf(gx[u], A[u].z, Fz);
+                    }
             }
         }
         __syncthreads();  // the next chunk overwrites the tables
@@ -456,6 +534,21 @@ __global__ __launch_bounds__(ALM_BLOCK) void k_alm_spread(const RotorDev *rots, 
     R.Fbox[c] = Fx;
     R.Fbox[nb + c] = Fy;
     R.Fbox[2 * nb + c] = Fz;
+}
+
+// Two launches per step: the point batches, then the spreading tiles, which
+// read every point's record. (Tried and dropped: one launch whose spreading
+// workgroups wait on an arrival counter of the point workgroups; the
+// device-scope fences and the wait cost more than the launch they save.)
+template <typename T, int PAR>
+__global__ __launch_bounds__(ALM_BLOCK) void k_alm_points(Geo g, Physics ph, RotorDev *rots, long t) {
+    __shared__ PointsLds L;
+    alm_points_wg<T, PAR>(g, ph, rots, t, (int)blockIdx.x, (int)blockIdx.y, L);
+}
+
+__global__ __launch_bounds__(ALM_BLOCK) void k_alm_spread(const RotorDev *rots, SpreadTiles st) {
+    __shared__ SpreadLds L;
+    alm_spread_wg(rots, st, (int)blockIdx.x, L);
 }
 
 template <typename T, int PAR>

@@ -520,6 +520,8 @@ int lbm_set_rotor(lbm_ctx *c, int id, const lbm_rotor *r) {
             D.n_polar = r->n_polar;
             D.alpha0 = a0;
             D.dalpha = da;
+            D.alpha0_f = (float)a0;
+            D.inv_dalpha_f = (float)(1.0 / da);
             D.r = R.d_r;
             D.chord = R.d_chord;
             D.twist = R.d_twist;
@@ -894,6 +896,8 @@ int lbm_set_turbine(lbm_ctx *c, int id, const lbm_turbine *tb) {
             D.n_polar = np_pol;
             D.alpha0 = a0;
             D.dalpha = da;
+            D.alpha0_f = (float)a0;
+            D.inv_dalpha_f = (float)(1.0 / da);
             D.cl = R.d_cl;
             D.cd = R.d_cd;
             D.nodes = R.d_nodes;

@@ -110,10 +110,11 @@ struct RotorDev {
     const NodeDev *nodes;       // turbine tree, or nullptr for a rotor
     const TreePointDev *tpts;   // [npts] turbine points
     double alpha0, dalpha;
+    float alpha0_f, inv_dalpha_f;  // the polar grid for the FP32 lookup
     const double *r, *chord, *twist, *dl;     // n_points
     const float *cl, *cd;                     // n_polar
     // outputs
-    float *pts;        // per point: x[3], F[3] (force on blade), c0[3] (as float), inv W
+    float *pts;        // per point: x - c0 [3], -F [3] (reaction on the flow), c0 [3] (nearest node, as float)
     double *pt_force;  // per point: F[3] in FP64 (turbine: TREE_PT_OUT values)
     double *loads;     // T, Q, P, then per batch of 32 points: partial T, Q
     // spreading box
