@@ -21,6 +21,22 @@ sys.path.insert(0, ROOT)
 from paper_2402_13171_amd import roofline  # noqa: E402
 
 
+def targets(results, base):
+    """The throughput targets of the workload, each with its measured value and
+    whether it is met: FP32 stream-collide at >= 80 % of the 8 TB/s HBM peak,
+    and the 16-bit-stored variants (with and without the learned closure) at
+    >= 1.7 times the FP32 MLUPS. Only variants that were run are listed."""
+    out = {}
+    if "f32" in results:
+        f = results["f32"]["hbm_frac"]
+        out["f32_frac_of_hbm_peak"] = {"value": round(f, 4), "target": 0.80, "met": bool(f >= 0.80)}
+    for k in ("f16", "bf16", "f16+mlp"):
+        if k in results and "f32" in results:
+            r = results[k]["mlups"] / base["mlups"]
+            out[f"{k}_vs_f32"] = {"value": round(r, 3), "target": 1.7, "met": bool(r >= 1.7)}
+    return out
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -258,6 +274,7 @@ def main():
                          "frac_of_pattern_probe": round(v["achieved_GBps"] / v["pattern_GBps"], 4)}
                      for k, v in results.items()},
     }
+    out["targets"] = targets(results, base)
     print(json.dumps(out), flush=True)
 
 
