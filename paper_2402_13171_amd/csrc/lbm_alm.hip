@@ -200,9 +200,9 @@ struct PointsLds {
 
 // batch bx of slot by
 template <typename T, int PAR>
-__device__ __forceinline__ void alm_points_wg(const Geo &g, const Physics &ph, RotorDev *rots, long t, int bx,
+__device__ __forceinline__ void alm_points_wg(const Geo &g, const Physics &ph, const RotorDev *rots, long t, int bx,
                                               int by, PointsLds &L) {
-    RotorDev &R = rots[by];
+    const RotorDev &R = rots[by];
     const int npts = R.npts;
     const int base = bx * ALM_BATCH;
     if (base >= npts) return;  // uniform across the workgroup
@@ -389,10 +389,21 @@ constexpr int SP_W = 2 * SUPPORT + 1;  // widest support (Gaussian), offsets -SU
 
 // One launch spreads every slot: workgroups [first[r], first[r+1]) take the
 // tiles of slot r (tile counts per axis in tiles[r]).
+// what the spreading workgroups read of each slot, passed by value (kernel
+// arguments) so that a workgroup needs no load of the slot table first
+struct SpreadSlot {
+    const float *pts;
+    float *Fbox;
+    ForceBox box;
+    int npts, half;
+    int roma;   // Roma delta (else Gaussian)
+    float ie2;  // Gaussian: 1 / eps^2
+};
 struct SpreadTiles {
     int nslots;
     int first[MAX_ROTORS + 1];
     int tx[MAX_ROTORS], ty[MAX_ROTORS];
+    SpreadSlot slot[MAX_ROTORS];
 };
 
 struct SpreadLds {
@@ -407,12 +418,11 @@ struct SpreadLds {
 };
 
 // the spreading workgroup blk of the launch (over all slots)
-__device__ __forceinline__ void alm_spread_wg(const RotorDev *rots, const SpreadTiles &st, int blk_all,
-                                              SpreadLds &L) {
+__device__ __forceinline__ void alm_spread_wg(const SpreadTiles &st, int blk_all, SpreadLds &L) {
     int rid = 0;
     while (rid + 1 < st.nslots && blk_all >= st.first[rid + 1]) ++rid;  // uniform per workgroup
     const int blk = blk_all - st.first[rid], tiles_x = st.tx[rid], tiles_y = st.ty[rid];
-    const RotorDev &R = rots[rid];
+    const SpreadSlot &R = st.slot[rid];
     const int npts = R.npts;
     const ForceBox &B = R.box;
     const int half = R.half, W = 2 * half + 1;  // half <= SUPPORT (checked on the host)
@@ -462,8 +472,8 @@ __device__ __forceinline__ void alm_spread_wg(const RotorDev *rots, const Spread
     const int X = X0 + (int)(threadIdx.x % SP_TX), Y = Y0 + (int)((threadIdx.x / SP_TX) % SP_TY),
               Z = Z0 + (int)(threadIdx.x / (SP_TX * SP_TY));
     const bool mine = X <= X1 && Y <= Y1 && Z <= Z1;  // threads past the box edge keep to the barriers
-    const float ie2 = R.kernel == LBM_KERNEL_GAUSS ? (float)(1.0 / (R.eps * R.eps)) : 0.0f;
-    const bool roma = R.kernel == LBM_KERNEL_ROMA3;  // uniform over the grid
+    const float ie2 = R.ie2;
+    const bool roma = R.roma != 0;  // uniform over the grid
     float Fx = 0.f, Fy = 0.f, Fz = 0.f;
     for (int c0 = 0; c0 < count; c0 += SP_CHUNK) {
         const int nk = min(SP_CHUNK, count - c0);
@@ -540,26 +550,34 @@ __device__ __forceinline__ void alm_spread_wg(const RotorDev *rots, const Spread
 // read every point's record. (Tried and dropped: one launch whose spreading
 // workgroups wait on an arrival counter of the point workgroups; the
 // device-scope fences and the wait cost more than the launch they save.)
+// every slot's parameters, passed by value (kernel arguments) so that a
+// workgroup needs no load of the slot table before its first dependent load
+struct RotorSet {
+    RotorDev r[MAX_ROTORS];
+};
+
 template <typename T, int PAR>
-__global__ __launch_bounds__(ALM_BLOCK) void k_alm_points(Geo g, Physics ph, RotorDev *rots, long t) {
+__global__ __launch_bounds__(ALM_BLOCK) void k_alm_points(Geo g, Physics ph, RotorSet rs, long t) {
     __shared__ PointsLds L;
-    alm_points_wg<T, PAR>(g, ph, rots, t, (int)blockIdx.x, (int)blockIdx.y, L);
+    alm_points_wg<T, PAR>(g, ph, rs.r, t, (int)blockIdx.x, (int)blockIdx.y, L);
 }
 
-__global__ __launch_bounds__(ALM_BLOCK) void k_alm_spread(const RotorDev *rots, SpreadTiles st) {
+__global__ __launch_bounds__(ALM_BLOCK) void k_alm_spread(SpreadTiles st) {
     __shared__ SpreadLds L;
-    alm_spread_wg(rots, st, (int)blockIdx.x, L);
+    alm_spread_wg(st, (int)blockIdx.x, L);
 }
 
 template <typename T, int PAR>
-static void alm_t(const Geo &g, const Physics &ph, const RotorDev *h_rots, RotorDev *d_rots, int nrot, long t,
+static void alm_t(const Geo &g, const Physics &ph, const RotorDev *h_rots, int nrot, long t,
                   hipStream_t s) {
     int nb = 1;
     for (int r = 0; r < nrot; ++r) {
         const int b = (h_rots[r].npts + ALM_BATCH - 1) / ALM_BATCH;
         nb = b > nb ? b : nb;
     }
-    k_alm_points<T, PAR><<<dim3(nb, nrot), ALM_BLOCK, 0, s>>>(g, ph, d_rots, t);
+    RotorSet rs{};
+    for (int r = 0; r < nrot; ++r) rs.r[r] = h_rots[r];
+    k_alm_points<T, PAR><<<dim3(nb, nrot), ALM_BLOCK, 0, s>>>(g, ph, rs, t);
     SpreadTiles st{};
     st.nslots = nrot;
     for (int r = 0; r < nrot; ++r) {
@@ -568,19 +586,28 @@ static void alm_t(const Geo &g, const Physics &ph, const RotorDev *h_rots, Rotor
         st.tx[r] = tx;
         st.ty[r] = ty;
         st.first[r + 1] = st.first[r] + tx * ty * tz;
+        const RotorDev &R = h_rots[r];
+        SpreadSlot &S = st.slot[r];
+        S.pts = R.pts;
+        S.Fbox = R.Fbox;
+        S.box = R.box;
+        S.npts = R.npts;
+        S.half = R.half;
+        S.roma = R.kernel == LBM_KERNEL_ROMA3;
+        S.ie2 = R.kernel == LBM_KERNEL_GAUSS ? (float)(1.0 / (R.eps * R.eps)) : 0.0f;
     }
-    k_alm_spread<<<(unsigned)st.first[nrot], ALM_BLOCK, 0, s>>>(d_rots, st);
+    k_alm_spread<<<(unsigned)st.first[nrot], ALM_BLOCK, 0, s>>>(st);
 }
 
-int launch_alm(int storage, int parity, const Geo &g, const Physics &ph, const RotorDev *h_rots, RotorDev *d_rots,
-               int nrot, long t, hipStream_t s) {
+int launch_alm(int storage, int parity, const Geo &g, const Physics &ph, const RotorDev *h_rots, int nrot,
+               long t, hipStream_t s) {
     switch (storage * 2 + parity) {
-        case 0: alm_t<float, 0>(g, ph, h_rots, d_rots, nrot, t, s); break;
-        case 1: alm_t<float, 1>(g, ph, h_rots, d_rots, nrot, t, s); break;
-        case 2: alm_t<__half, 0>(g, ph, h_rots, d_rots, nrot, t, s); break;
-        case 3: alm_t<__half, 1>(g, ph, h_rots, d_rots, nrot, t, s); break;
-        case 4: alm_t<bf16_t, 0>(g, ph, h_rots, d_rots, nrot, t, s); break;
-        case 5: alm_t<bf16_t, 1>(g, ph, h_rots, d_rots, nrot, t, s); break;
+        case 0: alm_t<float, 0>(g, ph, h_rots, nrot, t, s); break;
+        case 1: alm_t<float, 1>(g, ph, h_rots, nrot, t, s); break;
+        case 2: alm_t<__half, 0>(g, ph, h_rots, nrot, t, s); break;
+        case 3: alm_t<__half, 1>(g, ph, h_rots, nrot, t, s); break;
+        case 4: alm_t<bf16_t, 0>(g, ph, h_rots, nrot, t, s); break;
+        case 5: alm_t<bf16_t, 1>(g, ph, h_rots, nrot, t, s); break;
         default: return -1;
     }
     return hipGetLastError() == hipSuccess ? 0 : -2;

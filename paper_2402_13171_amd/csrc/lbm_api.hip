@@ -56,7 +56,6 @@ struct lbm_ctx {
     bool general_rates = false;
     float *d_ffield = nullptr;
     RotorHost rot[MAX_ROTORS];
-    RotorDev *d_rots = nullptr;  // compacted active rotors
     std::vector<RotorDev> h_rots;
     MlpDev *d_mlp = nullptr;
     bool mlp_set = false;
@@ -202,21 +201,11 @@ int ready(lbm_ctx *c) {
 }
 
 int refresh_rotor_table(lbm_ctx *c) {
+    // the active slots in slot order; the actuator-line kernels take them by
+    // value at each launch
     c->h_rots.clear();
-    std::vector<RotorDev> rots;
     for (int r = 0; r < MAX_ROTORS; ++r)
-        if (c->rot[r].on) rots.push_back(c->rot[r].dev);
-    if (rots.empty()) return LBM_OK;
-    if (!c->d_rots) {
-        if (hipMalloc((void **)&c->d_rots, sizeof(RotorDev) * MAX_ROTORS) != hipSuccess)
-            return fail(c, LBM_ENOMEM, "rotor table");
-    }
-    // the host list (which drives the launches) only names slots whose
-    // device table entry was written
-    HIPCHK(c, hipMemcpyAsync(c->d_rots, rots.data(), sizeof(RotorDev) * rots.size(), hipMemcpyHostToDevice,
-                             c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    c->h_rots = rots;
+        if (c->rot[r].on) c->h_rots.push_back(c->rot[r].dev);
     return LBM_OK;
 }
 
@@ -341,7 +330,6 @@ int lbm_destroy(lbm_ctx *c) {
         // was never attached has enqueued none)
         if (c->stream && (c->attached || c->own_stream)) (void)hipStreamSynchronize(c->stream);
         for (int r = 0; r < MAX_ROTORS; ++r) free_rotor(c->rot[r]);
-        if (c->d_rots) (void)hipFree(c->d_rots);
         if (c->d_ffield) (void)hipFree(c->d_ffield);
         if (c->d_mlp) (void)hipFree(c->d_mlp);
         if (c->d_stage) (void)hipFree(c->d_stage);
@@ -1057,7 +1045,7 @@ int lbm_step(lbm_ctx *c, int nsteps) {
                 return fail(c, LBM_EHIP, "inflow launch failed");
             g = geo_of(c);
             const int sr = c->cfg.rounding == LBM_ROUND_STOCHASTIC;
-            if (nrot > 0 && launch_alm(st, c->parity, g, ph, c->h_rots.data(), c->d_rots, nrot, c->t, c->stream))
+            if (nrot > 0 && launch_alm(st, c->parity, g, ph, c->h_rots.data(), nrot, c->t, c->stream))
                 return fail(c, LBM_EHIP, "actuator-line launch failed");
             if (launch_stream_collide(st, sr, c->parity, (int)c->cfg.closure, mode, frc, c->general_rates, g, ph,
                                       c->stream))

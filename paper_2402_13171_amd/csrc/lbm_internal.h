@@ -152,8 +152,8 @@ int launch_moments(int storage, int parity, const Geo &g, const Physics &ph, dou
                    int nblocks, double *out, hipStream_t s);
 int launch_check(int storage, int parity, const Geo &g, const Physics &ph, double *partials,
                  int nblocks, double mass0, double tol, int *flag, hipStream_t s);
-int launch_alm(int storage, int parity, const Geo &g, const Physics &ph, const RotorDev *h_rots,
-               RotorDev *d_rots, int nrot, long t, hipStream_t s);
+int launch_alm(int storage, int parity, const Geo &g, const Physics &ph, const RotorDev *h_rots, int nrot,
+               long t, hipStream_t s);
 constexpr int ALM_MAX_POINTS = 512;
 constexpr int ALM_BATCH_PTS = 32;  // actuator points per workgroup of k_alm_points
 constexpr int ALM_LOADS_LEN = 3 + 2 * (ALM_MAX_POINTS / ALM_BATCH_PTS);

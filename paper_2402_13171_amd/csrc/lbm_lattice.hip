@@ -99,9 +99,9 @@ __device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned total) {
 // z plane, tw in {64, 128, 256}; a wave is a 64-cell row segment. Wide tiles
 // keep the cache lines that odd-step shifted accesses split between
 // neighbouring row segments inside one workgroup.
-// A copy of g whose store base the compiler cannot see through (an empty
-// asm that claims to rewrite the scalar register pair), so that addresses
-// built from it are recomputed rather than kept live.
+// Empty asm statements that claim to rewrite a value (a vector or a scalar
+// register), so that addresses built from it are recomputed where they are
+// used rather than kept live from an earlier use.
 __device__ __forceinline__ void opaque_v(uint32_t &v) { asm volatile("" : "+v"(v)); }
 __device__ __forceinline__ void opaque_s(int &v) { asm volatile("" : "+s"(v)); }
 
