@@ -359,8 +359,9 @@ __device__ __forceinline__ void alm_points_wg(const Geo &g, const Physics &ph, c
 
 // Gather-form spreading over one slot's box: F(X) = sum_p (-F_p) eta(X - x_p) / W_p.
 // One workgroup per tile of SP_TX x SP_TY x SP_TZ box cells. The workgroup
-// first keeps, in point order, the points whose support reaches the tile
-// (a ballot compaction per wave, then the waves' counts in order). Both
+// first keeps the points whose support reaches the tile, those of even index
+// and then those of odd index, each in point order (a ballot compaction per
+// wave, then the waves' counts in order). Both
 // kernels are products of one factor per axis (the Gaussian's exponential
 // splits, Roma's delta is defined that way), so the workgroup tabulates, for
 // each kept point, the factor of every support offset on each axis in LDS
@@ -368,11 +369,14 @@ __device__ __forceinline__ void alm_points_wg(const Geo &g, const Physics &ph, c
 // the three table sums; the Roma delta's weights sum to one). The y and z
 // factors, 1 / W_p and -F_p are then combined once per (point, (y, z) row of
 // the tile), and each cell sums over the kept points g_x(X) times its row's
-// vector: the same terms, each rounded the same way wherever the tile
-// boundaries fall, in point order, so the result does not depend on the
-// tiling. Points are taken in chunks of SP_CHUNK.
+// vector. Two threads share a cell: one sums the points of even index, the
+// other those of odd index, each in point order, and the cell's force is the
+// even sum plus the odd sum: the same terms, each rounded the same way and
+// grouped the same way wherever the tile boundaries fall, so the result does
+// not depend on the tiling. Points are taken in chunks of SP_CHUNK.
 constexpr int SP_TX = 16, SP_TY = 4, SP_TZ = 4;
-static_assert(SP_TX * SP_TY * SP_TZ == ALM_BLOCK, "one cell per thread");
+constexpr int SP_CELLS = SP_TX * SP_TY * SP_TZ;
+constexpr int SP_BLOCK = 2 * SP_CELLS;  // two threads per cell
 constexpr int SP_CHUNK = 64;
 constexpr int SP_UNROLL = 8;
 constexpr int SP_ROWS = SP_TY * SP_TZ;  // (y, z) rows of SP_TX cells in a tile
@@ -411,7 +415,8 @@ struct SpreadLds {
     // the nearest node minus the support half-width, -F and (per chunk) 1 / W_p
     float off[ALM_MAX_PTS][3];
     KeptPoint k[ALM_MAX_PTS];
-    int wave[ALM_BLOCK / 64];
+    int wave[SP_BLOCK / 64];
+    float part[SP_CELLS][3];         // the odd-index sums of each cell
     float g[SP_CHUNK][3][SP_W];      // per-axis factors of a chunk of kept points
     float sum[SP_CHUNK][3];          // and their sums over the support
     float4 row[SP_CHUNK][SP_ROWS];   // y, z factors x 1/W_p x (-F_p) per tile row
@@ -438,39 +443,47 @@ __device__ __forceinline__ void alm_spread_wg(const SpreadTiles &st, int blk_all
     const int X1 = min(X0 + SP_TX, B.x0 + B.bnx) - 1, Y1 = min(Y0 + SP_TY, B.y0 + B.bny) - 1,
               Z1 = min(Z0 + SP_TZ, B.z0 + B.bnz) - 1;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    int count = 0;  // uniform across the workgroup
-    for (int k0 = 0; k0 < npts; k0 += ALM_BLOCK) {
-        const int p = k0 + threadIdx.x;
-        bool reach = false;
-        float rec[9];
-        if (p < npts) {
-            // the whole record in one round trip, kept in LDS if the point reaches the tile
-            const float *P = R.pts + (size_t)p * PT_STRIDE;
+    // kept points: those of even index first, then those of odd index, each
+    // group in point order
+    int count = 0, n_even = 0;  // uniform across the workgroup
+    for (int parity = 0; parity < 2; ++parity) {
+        for (int k0 = 0; k0 < npts; k0 += SP_BLOCK) {
+            const int p = k0 + threadIdx.x;
+            bool reach = false;
+            float rec[9];
+            if (p < npts && (p & 1) == parity) {
+                // the whole record in one round trip, kept in LDS if the point reaches the tile
+                const float *P = R.pts + (size_t)p * PT_STRIDE;
 #pragma unroll
-            for (int q = 0; q < 9; ++q) rec[q] = P[q];
-            const int cx = (int)rec[6], cy = (int)rec[7], cz = (int)rec[8];
-            reach = cx - half <= X1 && cx + half >= X0 && cy - half <= Y1 && cy + half >= Y0 && cz - half <= Z1 &&
-                    cz + half >= Z0;
-        }
-        const unsigned long long bal = __ballot(reach);
-        if (lane == 0) s_wave[wave] = __popcll(bal);
-        __syncthreads();
-        int off = count;
-        for (int w = 0; w < wave; ++w) off += s_wave[w];
-        if (reach) {
-            const int k = off + __popcll(bal & ((1ull << lane) - 1ull));
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                s_off[k][a] = rec[a];
-                s_k[k].f[a] = rec[3 + a];
-                s_k[k].c[a] = (int)rec[6 + a] - half;
+                for (int q = 0; q < 9; ++q) rec[q] = P[q];
+                const int cx = (int)rec[6], cy = (int)rec[7], cz = (int)rec[8];
+                reach = cx - half <= X1 && cx + half >= X0 && cy - half <= Y1 && cy + half >= Y0 &&
+                        cz - half <= Z1 && cz + half >= Z0;
             }
+            const unsigned long long bal = __ballot(reach);
+            if (lane == 0) s_wave[wave] = __popcll(bal);
+            __syncthreads();
+            int off = count;
+            for (int w = 0; w < wave; ++w) off += s_wave[w];
+            if (reach) {
+                const int k = off + __popcll(bal & ((1ull << lane) - 1ull));
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    s_off[k][a] = rec[a];
+                    s_k[k].f[a] = rec[3 + a];
+                    s_k[k].c[a] = (int)rec[6 + a] - half;
+                }
+            }
+            for (int w = 0; w < SP_BLOCK / 64; ++w) count += s_wave[w];
+            __syncthreads();
         }
-        for (int w = 0; w < ALM_BLOCK / 64; ++w) count += s_wave[w];
-        __syncthreads();
+        if (parity == 0) n_even = count;
     }
-    const int X = X0 + (int)(threadIdx.x % SP_TX), Y = Y0 + (int)((threadIdx.x / SP_TX) % SP_TY),
-              Z = Z0 + (int)(threadIdx.x / (SP_TX * SP_TY));
+    // two threads per cell: the first sums the kept points of even index, the
+    // second those of odd index (each in point order), and F = F_even + F_odd
+    const int cell = (int)threadIdx.x % SP_CELLS, grp = (int)threadIdx.x / SP_CELLS;
+    const int lo = grp == 0 ? 0 : n_even, hi = grp == 0 ? n_even : count;
+    const int X = X0 + cell % SP_TX, Y = Y0 + (cell / SP_TX) % SP_TY, Z = Z0 + cell / (SP_TX * SP_TY);
     const bool mine = X <= X1 && Y <= Y1 && Z <= Z1;  // threads past the box edge keep to the barriers
     const float ie2 = R.ie2;
     const bool roma = R.roma != 0;  // uniform over the grid
@@ -479,7 +492,7 @@ __device__ __forceinline__ void alm_spread_wg(const SpreadTiles &st, int blk_all
         const int nk = min(SP_CHUNK, count - c0);
         // factors: e = d - (x_p - node) for d = -half..half on each axis, one
         // thread per (point, axis), which also sums its row
-        for (int q = threadIdx.x; q < nk * 3; q += ALM_BLOCK) {
+        for (int q = threadIdx.x; q < nk * 3; q += SP_BLOCK) {
             const int k = q / 3, ax = q % 3;
             const float o = s_off[c0 + k][ax];
             float sa = 0.0f;
@@ -492,7 +505,7 @@ __device__ __forceinline__ void alm_spread_wg(const SpreadTiles &st, int blk_all
             s_sum[k][ax] = sa;
         }
         __syncthreads();
-        for (int q = threadIdx.x; q < nk; q += ALM_BLOCK) {
+        for (int q = threadIdx.x; q < nk; q += SP_BLOCK) {
             double S = 1.0;
             if (!roma)
                 for (int ax = 0; ax < 3; ++ax) S *= (double)s_sum[q][ax];
@@ -502,7 +515,7 @@ __device__ __forceinline__ void alm_spread_wg(const SpreadTiles &st, int blk_all
         // the y and z factors of each kept point for each (y, z) row of the
         // tile, times 1 / W_p and -F_p: one float4 per (point, row), with the
         // point's window start in x (zero where the row is outside its window)
-        for (int q = threadIdx.x; q < nk * SP_ROWS; q += ALM_BLOCK) {
+        for (int q = threadIdx.x; q < nk * SP_ROWS; q += SP_BLOCK) {
             const int k = q / SP_ROWS, r = q % SP_ROWS;
             const KeptPoint &P = s_k[c0 + k];
             const int dy = Y0 + r % SP_TY - P.c[1], dz = Z0 + r / SP_TY - P.c[2];
@@ -511,20 +524,22 @@ __device__ __forceinline__ void alm_spread_wg(const SpreadTiles &st, int blk_all
             s_row[k][r] = make_float4(a * P.f[0], a * P.f[1], a * P.f[2], __int_as_float(P.c[0]));
         }
         __syncthreads();
-        if (mine) {
+        // this thread's kept points within the chunk, as chunk positions
+        const int k_lo = max(lo, c0) - c0, k_hi = min(hi, c0 + nk) - c0;
+        if (mine && k_lo < k_hi) {
             // per cell: F += g_x(X) A(row); SP_UNROLL points at a time, so that
             // their LDS reads are in flight together, in point order
-            const int r = (int)threadIdx.x / SP_TX;
-            for (int k0 = 0; k0 < nk; k0 += SP_UNROLL) {
+            const int r = cell / SP_TX;
+            for (int k0 = k_lo; k0 < k_hi; k0 += SP_UNROLL) {
                 float gx[SP_UNROLL];
                 float4 A[SP_UNROLL];
                 bool in[SP_UNROLL];
 #pragma unroll
                 for (int u = 0; u < SP_UNROLL; ++u) {
-                    const int k = k0 + u < nk ? k0 + u : k0;  // past the end: a valid entry, not used
+                    const int k = k0 + u < k_hi ? k0 + u : k0;  // past the end: a valid entry, not used
                     A[u] = s_row[k][r];
                     const int dx = X - __float_as_int(A[u].w);
-                    in[u] = k0 + u < nk && (unsigned)dx < (unsigned)W;
+                    in[u] = k0 + u < k_hi && (unsigned)dx < (unsigned)W;
                     gx[u] = s_g[k][0][in[u] ? dx : 0];
                 }
 #pragma unroll
@@ -538,7 +553,17 @@ __device__ __forceinline__ void alm_spread_wg(const SpreadTiles &st, int blk_all
         }
         __syncthreads();  // the next chunk overwrites the tables
     }
-    if (!mine) return;
+    // the odd-index sums to the threads of the even-index ones
+    if (grp == 1) {
+        L.part[cell][0] = Fx;
+        L.part[cell][1] = Fy;
+        L.part[cell][2] = Fz;
+    }
+    __syncthreads();
+    if (grp == 1 || !mine) return;
+    Fx += L.part[cell][0];
+    Fy += L.part[cell][1];
+    Fz += L.part[cell][2];
     const size_t nb = (size_t)B.bnx * B.bny * B.bnz;
     const size_t c = (size_t)(X - B.x0) + (size_t)B.bnx * ((size_t)(Y - B.y0) + (size_t)B.bny * (size_t)(Z - B.z0));
     R.Fbox[c] = Fx;
@@ -562,7 +587,7 @@ __global__ __launch_bounds__(ALM_BLOCK) void k_alm_points(Geo g, Physics ph, Rot
     alm_points_wg<T, PAR>(g, ph, rs.r, t, (int)blockIdx.x, (int)blockIdx.y, L);
 }
 
-__global__ __launch_bounds__(ALM_BLOCK) void k_alm_spread(SpreadTiles st) {
+__global__ __launch_bounds__(SP_BLOCK) void k_alm_spread(SpreadTiles st) {
     __shared__ SpreadLds L;
     alm_spread_wg(st, (int)blockIdx.x, L);
 }
@@ -596,7 +621,7 @@ static void alm_t(const Geo &g, const Physics &ph, const RotorDev *h_rots, int n
         S.roma = R.kernel == LBM_KERNEL_ROMA3;
         S.ie2 = R.kernel == LBM_KERNEL_GAUSS ? (float)(1.0 / (R.eps * R.eps)) : 0.0f;
     }
-    k_alm_spread<<<(unsigned)st.first[nrot], ALM_BLOCK, 0, s>>>(st);
+    k_alm_spread<<<(unsigned)st.first[nrot], SP_BLOCK, 0, s>>>(st);
 }
 
 int launch_alm(int storage, int parity, const Geo &g, const Physics &ph, const RotorDev *h_rots, int nrot,
