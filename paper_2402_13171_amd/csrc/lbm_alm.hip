@@ -120,6 +120,17 @@ __device__ void tree_pose(const NodeDev *nodes, int node, double t, TreePose &P)
     }
 }
 
+// cos and sin of blade b's azimuth azimuth0 + omega t + 2 pi b / n_blades at
+// the launch's step, by angle addition from the step's cos, sin of
+// azimuth0 + omega t (computed on the host in FP64 per launch) and the
+// blade's offset (a table written when the rotor is set): no trigonometry on
+// the device
+__device__ __forceinline__ void blade_azimuth(const RotorDev &R, int b, double &ct, double &st) {
+    const double cb = R.blade_cs[2 * b], sb = R.blade_cs[2 * b + 1];
+    ct = R.cos_az * cb - R.sin_az * sb;
+    st = R.sin_az * cb + R.cos_az * sb;
+}
+
 // Position (and, with v != nullptr, velocity and the node pose) of point p
 // of slot R at time t: a rotor's blade element or a turbine point.
 __device__ __forceinline__ void slot_point(const RotorDev &R, const TreePose *poses, int p, double t, double xp[3],
@@ -141,11 +152,12 @@ __device__ __forceinline__ void slot_point(const RotorDev &R, const TreePose *po
         }
     } else {
         const int b = p / R.n_points, k = p % R.n_points;
-        const double th = R.azimuth0 + R.omega_rot * t + 2.0 * PI_D * b / R.n_blades;
         const double rr = R.r[k];
+        double ct, st;
+        blade_azimuth(R, b, ct, st);
         xp[0] = R.hub[0];
-        xp[1] = R.hub[1] + rr * cos(th);
-        xp[2] = R.hub[2] + rr * sin(th);
+        xp[1] = R.hub[1] + rr * ct;
+        xp[2] = R.hub[2] + rr * st;
     }
 }
 
@@ -211,13 +223,14 @@ __device__ __forceinline__ void alm_points_wg(const Geo &g, const Physics &ph, c
     NodeDev *s_nodes = L.nodes;
     // the blade data of the batch's points into registers, in flight with
     // the sampling
-    double pre_r = 0.0, pre_chord = 0.0, pre_dl = 0.0, pre_twist = 0.0;
+    double pre_r = 0.0, pre_chord = 0.0, pre_dl = 0.0, pre_twist = 0.0, pre_ct = 0.0, pre_st = 0.0;
     if (!R.nodes && threadIdx.x < ALM_BATCH && base + (int)threadIdx.x < npts) {
-        const int k = (base + (int)threadIdx.x) % R.n_points;
+        const int k = (base + (int)threadIdx.x) % R.n_points, b = (base + (int)threadIdx.x) / R.n_points;
         pre_r = R.r[k];
         pre_chord = R.chord[k];
         pre_dl = R.dl[k];
         pre_twist = R.twist[k];
+        blade_azimuth(R, b, pre_ct, pre_st);
     }
     if (R.nodes) {
         // one coalesced copy of the node table, so that the pose recursion
@@ -258,11 +271,9 @@ __device__ __forceinline__ void alm_points_wg(const Geo &g, const Physics &ph, c
             TreePose P;
             double ct = 0.0, st = 0.0;  // rotor: cos, sin of the blade's azimuth
             if (!R.nodes) {
-                // slot_point's arithmetic, with the radius loaded at the start
-                const int b = p / R.n_points;
-                const double th = R.azimuth0 + R.omega_rot * (double)t + 2.0 * PI_D * b / R.n_blades;
-                ct = cos(th);
-                st = sin(th);
+                // slot_point's arithmetic, with the radius and azimuth loaded at the start
+                ct = pre_ct;
+                st = pre_st;
                 xp[0] = R.hub[0];
                 xp[1] = R.hub[1] + pre_r * ct;
                 xp[2] = R.hub[2] + pre_r * st;
@@ -601,7 +612,12 @@ static void alm_t(const Geo &g, const Physics &ph, const RotorDev *h_rots, int n
         nb = b > nb ? b : nb;
     }
     RotorSet rs{};
-    for (int r = 0; r < nrot; ++r) rs.r[r] = h_rots[r];
+    for (int r = 0; r < nrot; ++r) {
+        rs.r[r] = h_rots[r];
+        const double az = h_rots[r].azimuth0 + h_rots[r].omega_rot * (double)t;
+        rs.r[r].cos_az = cos(az);
+        rs.r[r].sin_az = sin(az);
+    }
     k_alm_points<T, PAR><<<dim3(nb, nrot), ALM_BLOCK, 0, s>>>(g, ph, rs, t);
     SpreadTiles st{};
     st.nslots = nrot;

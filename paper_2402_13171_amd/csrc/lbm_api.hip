@@ -26,6 +26,7 @@ struct RotorHost {
     double *d_r = nullptr, *d_chord = nullptr, *d_twist = nullptr, *d_dl = nullptr;
     float *d_cl = nullptr, *d_cd = nullptr, *d_pts = nullptr, *d_Fbox = nullptr;
     double *d_ptf = nullptr, *d_loads = nullptr;
+    double *d_bcs = nullptr;             // rotor: cos, sin of each blade's azimuth offset 2 pi b / B
     size_t ptf_len = 0;                  // doubles in d_ptf
     // turbine tree (Sec. 3.3): device nodes and points, node of each point
     NodeDev *d_nodes = nullptr;
@@ -210,7 +211,7 @@ int refresh_rotor_table(lbm_ctx *c) {
 }
 
 void free_rotor(RotorHost &R) {
-    void *ptrs[] = {R.d_r,   R.d_chord, R.d_twist, R.d_dl,    R.d_cl,   R.d_cd,
+    void *ptrs[] = {R.d_bcs, R.d_r,   R.d_chord, R.d_twist, R.d_dl,    R.d_cl,   R.d_cd,
                     R.d_pts, R.d_Fbox,  R.d_ptf,   R.d_loads, R.d_nodes, R.d_tpts};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -471,11 +472,19 @@ int lbm_set_rotor(lbm_ctx *c, int id, const lbm_rotor *r) {
                       hipMalloc((void **)&R.d_pts, (size_t)npts * PT_STRIDE * sizeof(float)) == hipSuccess &&
                       hipMalloc((void **)&R.d_ptf, (size_t)npts * 3 * sizeof(double)) == hipSuccess &&
                       hipMalloc((void **)&R.d_loads, ALM_LOADS_LEN * sizeof(double)) == hipSuccess &&
-                      hipMalloc((void **)&R.d_Fbox, (size_t)nb * 3 * sizeof(float)) == hipSuccess;
+                      hipMalloc((void **)&R.d_Fbox, (size_t)nb * 3 * sizeof(float)) == hipSuccess &&
+                      hipMalloc((void **)&R.d_bcs, (size_t)r->n_blades * 2 * sizeof(double)) == hipSuccess;
             if (!ok) {
                 free_rotor(R);
                 return fail(c, LBM_ENOMEM, "rotor buffers");
             }
+            std::vector<double> bcs(2 * (size_t)r->n_blades);
+            for (int b = 0; b < r->n_blades; ++b) {
+                const double phi = 2.0 * M_PI * b / r->n_blades;
+                bcs[2 * b] = cos(phi);
+                bcs[2 * b + 1] = sin(phi);
+            }
+            HIPCHK(c, hipMemcpy(R.d_bcs, bcs.data(), bcs.size() * sizeof(double), hipMemcpyHostToDevice));
             std::vector<float> cl(r->n_polar), cd(r->n_polar);
             for (int k = 0; k < r->n_polar; ++k) {
                 cl[k] = (float)r->cl[k];
@@ -514,6 +523,7 @@ int lbm_set_rotor(lbm_ctx *c, int id, const lbm_rotor *r) {
             D.chord = R.d_chord;
             D.twist = R.d_twist;
             D.dl = R.d_dl;
+            D.blade_cs = R.d_bcs;
             D.cl = R.d_cl;
             D.cd = R.d_cd;
             D.pts = R.d_pts;

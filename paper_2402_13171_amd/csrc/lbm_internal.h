@@ -112,6 +112,8 @@ struct RotorDev {
     double alpha0, dalpha;
     float alpha0_f, inv_dalpha_f;  // the polar grid for the FP32 lookup
     const double *r, *chord, *twist, *dl;     // n_points
+    const double *blade_cs;                   // rotor: cos, sin of 2 pi b / n_blades per blade
+    double cos_az, sin_az;                    // rotor: cos, sin of azimuth0 + omega t (set per launch)
     const float *cl, *cd;                     // n_polar
     // outputs
     float *pts;        // per point: x - c0 [3], -F [3] (reaction on the flow), c0 [3] (nearest node, as float)
