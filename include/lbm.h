@@ -345,8 +345,9 @@ const char *lbm_mlp_last_error(const lbm_mlp *m);
  * lbm_state_bytes gives the size. Restore into a context with the same
  * configuration and the same rotors and turbines set: a state of another
  * grid shape (even with the same cell count), another storage type or other
- * force boxes gives LBM_EINVAL, checked before any device work.
- * Synchronises. */
+ * force boxes gives LBM_EINVAL, checked before any device work; so does a
+ * state written by a library version with another population layout (the
+ * header's first word names the layout). Synchronises. */
 int lbm_state_bytes(const lbm_ctx *ctx, size_t *bytes);
 int lbm_get_state(lbm_ctx *ctx, void *host_buf, size_t bytes);
 int lbm_set_state(lbm_ctx *ctx, const void *host_buf, size_t bytes);
@@ -367,7 +368,8 @@ int lbm_copy_probe(const void *d_src, void *d_dst, size_t bytes, void *stream);
  * neighbours' slots, periodic wrap) with the same tiling and addressing and
  * no collision. Moves 27 * 2 * sizeof(storage) bytes per cell. The
  * populations are left permuted: initialise again before stepping. Needs the
- * 32-bit-offset layout (one population plane below 4 GiB). */
+ * 32-bit offsets of the fast path (one z plane of the store, ny * ceil(nx/64)
+ * blocks of 27 * 64 values, below 4 GiB); otherwise LBM_EINVAL. */
 int lbm_pattern_probe(lbm_ctx *ctx, int parity);
 
 const char *lbm_strerror(int code);
