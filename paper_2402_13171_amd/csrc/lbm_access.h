@@ -210,33 +210,49 @@ __device__ __forceinline__ void st_nbr(const Geo &g, const Nbr &n, int dx, int d
     if constexpr (sizeof(T) == 4) *lane_f32(p) = v;
     else Store<T>::st((T *)p, v);
 }
-// the cell's own slot 0 (its 27 slots follow at strides of BLK elements)
-__device__ __forceinline__ global_f32 *own_f32(const Geo &g, const Nbr &n) {
-    return lane_f32((const float *)g.pops + n.zb[1] + n.ys[1] + n.xo[1]);
+// slot i of the cell itself (the even step), every storage type in the
+// scalar-base form: one scalar base per direction and the lane's 32-bit
+// offset. For FP32 the base is made opaque (empty asm on a scalar register
+// pair) so that the compiler keeps that form: left alone it folds the
+// directions' distances (i * 256 bytes, beyond the instruction's immediate
+// offset from i = 16 on) into per-lane 64-bit addresses for part of the loads.
+template <typename T>
+__device__ __forceinline__ const char *own_plane(const Geo &g, const Nbr &n, int i) {
+    return (const char *)g.pops + n.zb[1] * sizeof(T) + (size_t)i * BLK * sizeof(T);
+}
+template <typename T>
+__device__ __forceinline__ float ld_own(const Geo &g, const Nbr &n, int i) {
+    const uint32_t off = (n.ys[1] + n.xo[1]) * (uint32_t)sizeof(T);
+    if constexpr (sizeof(T) == 4) {
+        uint64_t b = (uint64_t)own_plane<T>(g, n, i);
+        asm volatile("" : "+s"(b));
+        return *(const global_f32 *)((b + off));
+    } else {
+        return Store<T>::ld((const T *)(own_plane<T>(g, n, i) + off));
+    }
+}
+template <typename T>
+__device__ __forceinline__ void st_own(const Geo &g, const Nbr &n, int i, float v) {
+    const uint32_t off = (n.ys[1] + n.xo[1]) * (uint32_t)sizeof(T);
+    if constexpr (sizeof(T) == 4) {
+        uint64_t b = (uint64_t)own_plane<T>(g, n, i);
+        asm volatile("" : "+s"(b));
+        *(global_f32 *)(b + off) = v;
+    } else {
+        Store<T>::st((T *)(own_plane<T>(g, n, i) + off), v);
+    }
 }
 
 template <typename T, int I>
 struct Unroll32 {
     // even step: the cell's own slots
     static __device__ __forceinline__ void read_natural(const Geo &g, const Nbr &n, float *d) {
-        if constexpr (sizeof(T) == 4) {  // one per-lane base, the slots at constant offsets
-            const global_f32 *b = own_f32(g, n);
-#pragma unroll
-            for (int i = 0; i < 27; ++i) d[i] = b[i * BLK];
-        } else {
-            d[I] = ld_nbr<T>(g, n, 0, 0, 0, I);
-            Unroll32<T, I + 1>::read_natural(g, n, d);
-        }
+        d[I] = ld_own<T>(g, n, I);
+        Unroll32<T, I + 1>::read_natural(g, n, d);
     }
     static __device__ __forceinline__ void write_swap_local(const Geo &g, const Nbr &n, const float *o) {
-        if constexpr (sizeof(T) == 4) {
-            global_f32 *b = own_f32(g, n);
-#pragma unroll
-            for (int i = 0; i < 27; ++i) b[(26 - i) * BLK] = o[i];
-        } else {
-            st_nbr<T>(g, n, 0, 0, 0, 26 - I, o[I]);
-            Unroll32<T, I + 1>::write_swap_local(g, n, o);
-        }
+        st_own<T>(g, n, 26 - I, o[I]);
+        Unroll32<T, I + 1>::write_swap_local(g, n, o);
     }
     // odd step: slot 26 - I of x - c_I, and the push into slot I of x + c_I
     static __device__ __forceinline__ void read_periodic(const Geo &g, const Nbr &n, float *d) {
