@@ -216,6 +216,8 @@ __device__ __forceinline__ void st_nbr(const Geo &g, const Nbr &n, int dx, int d
 // pair) so that the compiler keeps that form: left alone it folds the
 // directions' distances (i * 256 bytes, beyond the instruction's immediate
 // offset from i = 16 on) into per-lane 64-bit addresses for part of the loads.
+// The cell's z, and so the base, must be the same across the wave (one z
+// plane per workgroup, as in the stream-collide tiles).
 template <typename T>
 __device__ __forceinline__ const char *own_plane(const Geo &g, const Nbr &n, int i) {
     return (const char *)g.pops + n.zb[1] * sizeof(T) + (size_t)i * BLK * sizeof(T);
