@@ -591,6 +591,9 @@ __device__ __forceinline__ void alm_spread_wg(const SpreadTiles &st, int blk_all
 struct RotorSet {
     RotorDev r[MAX_ROTORS];
 };
+// kernel arguments are limited to 4 KiB
+static_assert(sizeof(Geo) + sizeof(Physics) + sizeof(RotorSet) + sizeof(long) <= 4096, "points-kernel arguments");
+static_assert(sizeof(SpreadTiles) <= 4096, "spreading-kernel arguments");
 
 template <typename T, int PAR>
 __global__ __launch_bounds__(ALM_BLOCK) void k_alm_points(Geo g, Physics ph, RotorSet rs, long t) {
