@@ -100,10 +100,10 @@ int lbm_create(const lbm_config *cfg, lbm_ctx **out);
 int lbm_destroy(lbm_ctx *ctx);
 
 /* Bytes of caller-owned device memory lbm_attach needs: the population
- * store (blocked layout: each x row cut into blocks of 64 cells, rows padded
- * to whole blocks, a block's 27 directions stored one after the other, 64
- * values of the storage type each; nz * ny * ceil(nx / 64) * 1728 values,
- * rounded up to 256 bytes) and the auxiliary area (outflow ghost plane, inlet
+ * store (blocked layout: each x row cut into blocks of W cells, W = 32 for
+ * FP32 storage and 64 for 16-bit storage, rows padded to whole blocks, a
+ * block's 27 directions stored one after the other, W values of the storage
+ * type each; nz * ny * ceil(nx / W) * 27 W values, rounded up to 256 bytes) and the auxiliary area (outflow ghost plane, inlet
  * plane, reduction partials and flags). */
 int lbm_required_bytes(const lbm_ctx *ctx, size_t *pop_bytes, size_t *aux_bytes);
 

@@ -14,19 +14,28 @@ __device__ __forceinline__ size_t cidx(const Geo &g, int x, int y, int z) {
     return ((size_t)z * g.ny + y) * g.nx + x;
 }
 
-// Blocked population layout: the x rows are cut into blocks of BLK cells, and
-// a block keeps its 27 directions one after the other, BLK values each:
-// store[z][y][x / BLK][i][x % BLK] (rows padded to g.nbx whole blocks). A wave
-// of 64 cells of one row then reads and writes one contiguous 27 BLK region
-// in an even step, instead of 27 streams spread over the whole store.
-constexpr int BLK = 64;
-constexpr int BLK_SLOTS = 27 * BLK;
+// Blocked population layout: the x rows are cut into blocks of W cells, and
+// a block keeps its 27 directions one after the other, W values each:
+// store[z][y][x / W][i][x % W] (rows padded to g.nbx whole blocks), W =
+// blk_width(element size). A wave of 64 cells of one row then reads and
+// writes one or two contiguous 27 W regions in an even step, instead of 27
+// streams spread over the whole store.
+template <typename T>
+struct Blk {
+    static constexpr int W = blk_width((int)sizeof(T));
+    static constexpr int LOG = W == 32 ? 5 : (W == 64 ? 6 : 7);
+    static constexpr int SLOTS = 27 * W;
+    static_assert((1 << LOG) == W, "power-of-two block width");
+};
+template <typename T>
 __device__ __forceinline__ size_t slot_idx(const Geo &g, int i, int x, int y, int z) {
-    return (((size_t)z * g.ny + y) * g.nbx + (size_t)(x >> 6)) * BLK_SLOTS + (size_t)(i * BLK + (x & (BLK - 1)));
+    return (((size_t)z * g.ny + y) * g.nbx + (size_t)(x >> Blk<T>::LOG)) * Blk<T>::SLOTS +
+           (size_t)(i * Blk<T>::W + (x & (Blk<T>::W - 1)));
 }
 // element offset of cell x's slot 0 within its row of blocks
+template <typename T>
 __device__ __forceinline__ uint32_t row_xpart(int x) {
-    return (uint32_t)(x >> 6) * (uint32_t)BLK_SLOTS + (uint32_t)(x & (BLK - 1));
+    return (uint32_t)(x >> Blk<T>::LOG) * (uint32_t)Blk<T>::SLOTS + (uint32_t)(x & (Blk<T>::W - 1));
 }
 
 __device__ __forceinline__ float phi1(int c, float u) {
@@ -49,7 +58,7 @@ __device__ __forceinline__ float read_swapped(const Geo &g, int x, int y, int z)
     bool refl = false;
     if (cz != 0 && (sz < 0 || sz >= g.nz)) {
         const int bc = sz < 0 ? g.bc_zlo : g.bc_zhi;
-        if (bc == BC_NOSLIP) return Store<T>::ld(pops + slot_idx(g, I, x, y, z));
+        if (bc == BC_NOSLIP) return Store<T>::ld(pops + slot_idx<T>(g, I, x, y, z));
         if (bc == BC_FREESLIP) {
             refl = true;
             sz = z;
@@ -69,7 +78,7 @@ __device__ __forceinline__ float read_swapped(const Geo &g, int x, int y, int z)
             return Store<T>::ld(G + (size_t)(ii / 3) * g.ny * g.nz + sy + (size_t)g.ny * sz);
         }
     }
-    return Store<T>::ld(pops + slot_idx(g, 26 - ii, sx, sy, sz));
+    return Store<T>::ld(pops + slot_idx<T>(g, 26 - ii, sx, sy, sz));
 }
 
 // Odd-step push of the post-collision deviation of direction I.
@@ -82,7 +91,7 @@ __device__ __forceinline__ void write_odd(const Geo &g, int x, int y, int z, flo
     if (cz != 0 && (tz < 0 || tz >= g.nz)) {
         const int bc = tz < 0 ? g.bc_zlo : g.bc_zhi;
         if (bc == BC_NOSLIP) {
-            Store<T>::st(pops + slot_idx(g, 26 - I, x, y, z), v);
+            Store<T>::st(pops + slot_idx<T>(g, 26 - I, x, y, z), v);
             return;
         }
         if (bc == BC_FREESLIP) {
@@ -97,7 +106,7 @@ __device__ __forceinline__ void write_odd(const Geo &g, int x, int y, int z, flo
         if (g.bc_x != BC_PERIODIC) return;
         tx = wrapi(tx, g.nx);
     }
-    Store<T>::st(pops + slot_idx(g, refl ? RI : I, tx, ty, tz), v);
+    Store<T>::st(pops + slot_idx<T>(g, refl ? RI : I, tx, ty, tz), v);
 }
 
 // Force on a cell: uniform part + optional dense field + rotor boxes.
@@ -133,9 +142,9 @@ __device__ __forceinline__ float omega1_of(const CellMoments &m, const Physics &
 template <typename T, int I>
 struct Unroll {
     // load/store helpers unrolled over the 27 directions at compile time;
-    // s0 is the element index of the cell's slot 0 (slot_idx(g, 0, x, y, z))
+    // s0 is the element index of the cell's slot 0 (slot_idx<T>(g, 0, x, y, z))
     static __device__ __forceinline__ void read_natural(const Geo &g, size_t s0, float *d) {
-        d[I] = Store<T>::ld((const T *)g.pops + s0 + I * BLK);
+        d[I] = Store<T>::ld((const T *)g.pops + s0 + I * Blk<T>::W);
         Unroll<T, I + 1>::read_natural(g, s0, d);
     }
     static __device__ __forceinline__ void read_sw(const Geo &g, int x, int y, int z, float *d) {
@@ -143,7 +152,7 @@ struct Unroll {
         Unroll<T, I + 1>::read_sw(g, x, y, z, d);
     }
     static __device__ __forceinline__ void write_swap_local(const Geo &g, size_t s0, const float *o) {
-        Store<T>::st((T *)g.pops + s0 + (26 - I) * BLK, o[I]);
+        Store<T>::st((T *)g.pops + s0 + (26 - I) * Blk<T>::W, o[I]);
         Unroll<T, I + 1>::write_swap_local(g, s0, o);
     }
     static __device__ __forceinline__ void write_push(const Geo &g, int x, int y, int z, const float *o) {
@@ -172,12 +181,13 @@ struct Nbr {
     uint32_t ys[3], xo[3];
     size_t zb[3];
 };
+template <typename T>
 __device__ __forceinline__ void fast_nbr(const Geo &g, int x, int y, int z, Nbr &n) {
     const int xm = x == 0 ? g.nx - 1 : x - 1, xp = x == g.nx - 1 ? 0 : x + 1;
-    n.xo[0] = row_xpart(xm);
-    n.xo[1] = row_xpart(x);
-    n.xo[2] = row_xpart(xp);
-    const uint32_t rowlen = (uint32_t)g.nbx * (uint32_t)BLK_SLOTS, yr = (uint32_t)y * rowlen;
+    n.xo[0] = row_xpart<T>(xm);
+    n.xo[1] = row_xpart<T>(x);
+    n.xo[2] = row_xpart<T>(xp);
+    const uint32_t rowlen = (uint32_t)g.nbx * (uint32_t)Blk<T>::SLOTS, yr = (uint32_t)y * rowlen;
     n.ys[0] = y == 0 ? (uint32_t)(g.ny - 1) * rowlen : yr - rowlen;
     n.ys[1] = yr;
     n.ys[2] = y == g.ny - 1 ? 0u : yr + rowlen;
@@ -198,14 +208,14 @@ __device__ __forceinline__ global_f32 *lane_f32(const void *p) {
 // slot i of the cell at (x + dx, y + dy, z + dz), dx, dy, dz in {-1, 0, 1}
 template <typename T>
 __device__ __forceinline__ float ld_nbr(const Geo &g, const Nbr &n, int dx, int dy, int dz, int i) {
-    const char *plane = (const char *)g.pops + n.zb[dz + 1] * sizeof(T) + (size_t)i * BLK * sizeof(T);
+    const char *plane = (const char *)g.pops + n.zb[dz + 1] * sizeof(T) + (size_t)i * Blk<T>::W * sizeof(T);
     const char *p = plane + (n.ys[dy + 1] + n.xo[dx + 1]) * (uint32_t)sizeof(T);
     if constexpr (sizeof(T) == 4) return *lane_f32(p);
     else return Store<T>::ld((const T *)p);
 }
 template <typename T>
 __device__ __forceinline__ void st_nbr(const Geo &g, const Nbr &n, int dx, int dy, int dz, int i, float v) {
-    char *plane = (char *)g.pops + n.zb[dz + 1] * sizeof(T) + (size_t)i * BLK * sizeof(T);
+    char *plane = (char *)g.pops + n.zb[dz + 1] * sizeof(T) + (size_t)i * Blk<T>::W * sizeof(T);
     char *p = plane + (n.ys[dy + 1] + n.xo[dx + 1]) * (uint32_t)sizeof(T);
     if constexpr (sizeof(T) == 4) *lane_f32(p) = v;
     else Store<T>::st((T *)p, v);
@@ -213,14 +223,15 @@ __device__ __forceinline__ void st_nbr(const Geo &g, const Nbr &n, int dx, int d
 // slot i of the cell itself (the even step), every storage type in the
 // scalar-base form: one scalar base per direction and the lane's 32-bit
 // offset. For FP32 the base is made opaque (empty asm on a scalar register
-// pair) so that the compiler keeps that form: left alone it folds the
-// directions' distances (i * 256 bytes, beyond the instruction's immediate
-// offset from i = 16 on) into per-lane 64-bit addresses for part of the loads.
+// pair), so that each direction keeps a scalar base of its own: left alone the
+// compiler shares one base and puts the directions' distances (i * 128 bytes)
+// in the instructions' immediate offsets, which measured 0.6 % slower per
+// step at 512^3.
 // The cell's z, and so the base, must be the same across the wave (one z
 // plane per workgroup, as in the stream-collide tiles).
 template <typename T>
 __device__ __forceinline__ const char *own_plane(const Geo &g, const Nbr &n, int i) {
-    return (const char *)g.pops + n.zb[1] * sizeof(T) + (size_t)i * BLK * sizeof(T);
+    return (const char *)g.pops + n.zb[1] * sizeof(T) + (size_t)i * Blk<T>::W * sizeof(T);
 }
 template <typename T>
 __device__ __forceinline__ float ld_own(const Geo &g, const Nbr &n, int i) {
@@ -289,7 +300,7 @@ struct Unroll32<T, 27> {
 // than 2^32 bytes), whose 27 loads are independent of each other.
 template <typename T>
 __device__ __forceinline__ bool swapped_read_is_plain(const Geo &g, int x, int z) {
-    const bool fits = (size_t)g.ny * (size_t)g.nbx * BLK_SLOTS * sizeof(T) < ((size_t)1 << 32);
+    const bool fits = (size_t)g.ny * (size_t)g.nbx * Blk<T>::SLOTS * sizeof(T) < ((size_t)1 << 32);
     const bool xin = g.bc_x == BC_PERIODIC || (x > 0 && x < g.nx - 1);
     const bool zlo = g.bc_zlo == BC_NOSLIP || g.bc_zlo == BC_FREESLIP;
     const bool zhi = g.bc_zhi == BC_NOSLIP || g.bc_zhi == BC_FREESLIP;
@@ -299,10 +310,10 @@ __device__ __forceinline__ bool swapped_read_is_plain(const Geo &g, int x, int z
 template <typename T, int PAR>
 __device__ __forceinline__ void read_cell(const Geo &g, size_t cell, int x, int y, int z, float *d) {
     if (PAR == 0) {
-        Unroll<T, 0>::read_natural(g, slot_idx(g, 0, x, y, z), d);
+        Unroll<T, 0>::read_natural(g, slot_idx<T>(g, 0, x, y, z), d);
     } else if (swapped_read_is_plain<T>(g, x, z)) {
         Nbr n;
-        fast_nbr(g, x, y, z, n);
+        fast_nbr<T>(g, x, y, z, n);
         Unroll32<T, 0>::read_periodic(g, n, d);
     } else {
         Unroll<T, 0>::read_sw(g, x, y, z, d);

@@ -44,7 +44,7 @@ struct lbm_ctx {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     size_t n = 0, esize = 4;
-    int nbx = 0;          // blocks of 64 cells per x row
+    int nbx = 0;          // blocks of blk_width(esize) cells per x row
     size_t zplane = 0;    // elements per z plane of the blocked store
     size_t pop_bytes = 0, aux_bytes = 0;
     size_t off_ghost = 0, off_uin = 0, off_part = 0, off_flag = 0;
@@ -296,8 +296,9 @@ int lbm_create(const lbm_config *cfg, lbm_ctx **out) {
         x->cfg = c;
         x->n = n;
         x->esize = c.storage == LBM_F32 ? 4 : 2;
-        x->nbx = (c.nx + 63) / 64;
-        x->zplane = (size_t)c.ny * (size_t)x->nbx * 27 * 64;
+        const int bw = blk_width((int)x->esize);
+        x->nbx = (c.nx + bw - 1) / bw;
+        x->zplane = (size_t)c.ny * (size_t)x->nbx * 27 * bw;
         x->pop_bytes = round_up((size_t)c.nz * x->zplane * x->esize, 256);
         x->omega2 = c.omega_hi[0] == 0.0 ? 1.0f : (float)c.omega_hi[0];
         for (int k = 0; k < 8; ++k) {
@@ -1274,7 +1275,7 @@ int lbm_set_closure_weights(lbm_ctx *c, const float *w, size_t n) {
 }
 
 // checkpoint header: magic, time, parity, storage, force-box bytes, nx, ny, nz
-constexpr long STATE_MAGIC = 0x4c424d33L;  // blocked population layout
+constexpr long STATE_MAGIC = 0x4c424d34L;  // blocked population layout, 32-cell FP32 blocks
 
 // bytes of the force boxes of the active rotor / turbine slots (slot order)
 static size_t box_state_bytes(const lbm_ctx *c) {

@@ -12,6 +12,11 @@ constexpr int MLP_NBLOB = 1326;
 
 enum Bc { BC_PERIODIC = 0, BC_INOUT = 1, BC_NOSLIP = 2, BC_FREESLIP = 3 };
 
+// Cells per block of the blocked population layout (lbm_access.h) for an
+// element size in bytes: 32 for FP32 storage (a direction's run in a block is
+// one 128-byte line), 64 for 16-bit storage.
+__host__ __device__ constexpr int blk_width(int esize) { return esize == 4 ? 32 : 64; }
+
 // 32-bit finaliser of MurmurHash3 (Appleby): the random words of the
 // stochastic rounding of 16-bit stores (per-step seed on the host, per cell
 // on the device) and SR_WEYL, the golden-ratio Weyl increment between them.
@@ -51,7 +56,7 @@ void mlp_pack(const float *blob, MlpDev *out);
 // Everything a lattice kernel needs, passed by value.
 struct Geo {
     void *pops;          // population store (storage type), blocked layout (lbm_access.h)
-    int nbx;             // blocks of 64 cells per x row (nx rounded up)
+    int nbx;             // blocks per x row (nx rounded up to blk_width cells)
     int nx, ny, nz;
     int bc_x, bc_zlo, bc_zhi;
     const float *uin_rd; // inlet velocity plane [3][ny*nz] of the streaming a swapped-layout read completes

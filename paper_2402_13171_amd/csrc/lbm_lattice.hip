@@ -53,7 +53,7 @@ __device__ __forceinline__ void odd_boundary_extras(const Geo &g, int x, int y, 
                 }
             }
             const int sy = wrapi(y - cy, g.ny);
-            Store<T>::st(pops + slot_idx(g, I, 0, y, z), inlet_dev(g, g.uin_wr, ii, sy, sz));
+            Store<T>::st(pops + slot_idx<T>(g, I, 0, y, z), inlet_dev(g, g.uin_wr, ii, sy, sz));
         }
     }
     if (x == g.nx - 1) {
@@ -67,12 +67,12 @@ __device__ __forceinline__ void odd_boundary_extras(const Geo &g, int x, int y, 
                 const int bc = tz < 0 ? g.bc_zlo : g.bc_zhi;
                 if (bc == BC_NOSLIP) continue;
                 if (bc == BC_FREESLIP) {
-                    Store<T>::st(pops + slot_idx(g, refl_z(J), x, ty, z), o[J]);
+                    Store<T>::st(pops + slot_idx<T>(g, refl_z(J), x, ty, z), o[J]);
                     continue;
                 }
                 tz = wrapi(tz, g.nz);
             }
-            Store<T>::st(pops + slot_idx(g, J, x, ty, tz), o[J]);
+            Store<T>::st(pops + slot_idx<T>(g, J, x, ty, tz), o[J]);
         }
     }
 }
@@ -169,8 +169,8 @@ __device__ __forceinline__ void write_odd_staged(const Geo &g, int x, const Nbr 
     const int x_lo = x0 == 0 ? g.nx - 1 : x0 - 1;      // x0 - 1, wrapped
     const int x_hi = x0 + 256 == g.nx ? 0 : x0 + 256;  // x0 + 256, wrapped
     const bool last = t == 255u, first = t == 0u;
-    const uint32_t xm = last ? row_xpart(x_lo) : n.xo[1], im = last ? 0u : t + 1u;   // c_x = -1
-    const uint32_t xp = first ? row_xpart(x_hi) : n.xo[1], ip = first ? 257u : t + 1u;  // c_x = +1
+    const uint32_t xm = last ? row_xpart<T>(x_lo) : n.xo[1], im = last ? 0u : t + 1u;   // c_x = -1
+    const uint32_t xp = first ? row_xpart<T>(x_hi) : n.xo[1], ip = first ? 257u : t + 1u;  // c_x = +1
     const bool keep_m = !(XO && last && x0 == 0), keep_p = !(XO && first && x0 + 256 == g.nx);
 #pragma unroll
     for (int j = 0; j < 9; ++j) {
@@ -178,8 +178,8 @@ __device__ __forceinline__ void write_odd_staged(const Geo &g, int x, const Nbr 
         // row y + c_y of the z plane z + c_z
         const int cy = cy_of(3 * j), cz = cz_of(3 * j);
         const uint32_t r = n.ys[1 + cy];
-        const char *pm = (const char *)g.pops + (n.zb[1 + cz] + (size_t)(3 * j) * BLK) * sizeof(T);
-        const char *pp = (const char *)g.pops + (n.zb[1 + cz] + (size_t)(3 * j + 2) * BLK) * sizeof(T);
+        const char *pm = (const char *)g.pops + (n.zb[1 + cz] + (size_t)(3 * j) * Blk<T>::W) * sizeof(T);
+        const char *pp = (const char *)g.pops + (n.zb[1 + cz] + (size_t)(3 * j + 2) * Blk<T>::W) * sizeof(T);
         const T vm = stage[j * STAGE_W + im], vp = stage[(9 + j) * STAGE_W + ip];
         if (keep_m) *(T *)(pm + (r + xm) * (uint32_t)sizeof(T)) = vm;
         if (keep_p) *(T *)(pp + (r + xp) * (uint32_t)sizeof(T)) = vp;
@@ -195,13 +195,13 @@ __device__ __forceinline__ void cell_update(const Geo &g, const Physics &ph, int
     Nbr n;  // fast path (no boundary rules in the addressing), see Unroll32
     if (PAR == 0) {
         if (BCG) {
-            Unroll<T, 0>::read_natural(g, slot_idx(g, 0, x, y, z), d);
+            Unroll<T, 0>::read_natural(g, slot_idx<T>(g, 0, x, y, z), d);
         } else {
-            fast_nbr(g, x, y, z, n);
+            fast_nbr<T>(g, x, y, z, n);
             Unroll32<T, 0>::read_natural(g, n, d);
         }
     } else if (!BCG) {
-        fast_nbr(g, x, y, z, n);
+        fast_nbr<T>(g, x, y, z, n);
         Unroll32<T, 0>::read_periodic(g, n, d);
         if (XO) open_x_sources<T>(g, x, y, z, d);
     } else {
@@ -237,12 +237,12 @@ __device__ __forceinline__ void cell_update(const Geo &g, const Physics &ph, int
         opaque_v(xo);
         opaque_v(yo);
         opaque_s(zo);
-        fast_nbr(g, (int)xo, (int)yo, zo, n);
+        fast_nbr<T>(g, (int)xo, (int)yo, zo, n);
     }
     const Geo &gw = g;
 
     if (PAR == 0) {
-        if (BCG) Unroll<T, 0>::write_swap_local(g, slot_idx(g, 0, x, y, z), o);
+        if (BCG) Unroll<T, 0>::write_swap_local(g, slot_idx<T>(g, 0, x, y, z), o);
         else Unroll32<T, 0>::write_swap_local(gw, n, o);
         if ((BCG || XO) && g.bc_x == BC_INOUT && x == g.nx - 1) {
             T *G = (T *)g.ghost;
@@ -336,7 +336,7 @@ __global__ __launch_bounds__(256) void k_pattern_probe(Geo g, unsigned gx, unsig
     if (x >= g.nx || y >= g.ny) return;
     float d[27];
     Nbr n;
-    fast_nbr(g, x, y, z, n);
+    fast_nbr<T>(g, x, y, z, n);
     if (PAR == 0) {
         Unroll32<T, 0>::read_natural(g, n, d);
         Unroll32<T, 0>::write_swap_local(g, n, d);
@@ -487,13 +487,13 @@ template <typename T>
 __device__ __forceinline__ void store_eq(const Geo &g, size_t cell, double rho, double ux, double uy, double uz) {
     T *pops = (T *)g.pops;
     const int x = (int)(cell % g.nx), y = (int)((cell / g.nx) % g.ny), z = (int)(cell / ((size_t)g.nx * g.ny));
-    const size_t s0 = slot_idx(g, 0, x, y, z);
+    const size_t s0 = slot_idx<T>(g, 0, x, y, z);
 #pragma unroll
     for (int i = 0; i < 27; ++i) {
         const double w = (cx_of(i) == 0 ? 2.0 / 3.0 : 1.0 / 6.0) * (cy_of(i) == 0 ? 2.0 / 3.0 : 1.0 / 6.0) *
                          (cz_of(i) == 0 ? 2.0 / 3.0 : 1.0 / 6.0);
         const double fe = rho * phi1d(cx_of(i), ux) * phi1d(cy_of(i), uy) * phi1d(cz_of(i), uz);
-        Store<T>::st(pops + s0 + (size_t)i * BLK, (float)(fe - w));
+        Store<T>::st(pops + s0 + (size_t)i * Blk<T>::W, (float)(fe - w));
     }
 }
 

@@ -105,18 +105,20 @@ def test_state_of_another_shape_or_storage_is_refused_before_device_work():
         assert L.lbm_state_bytes(h, ctypes.byref(nb)) == lbm.OK
         buf = np.zeros(nb.value, dtype=np.uint8)
         hdr = buf[:64].view(np.int64)
-        hdr[:8] = [0x4c424d33, 5, 1, 0, 0, 32, 16, 8]       # a 32 x 16 x 8 grid: same cell count
+        hdr[:8] = [0x4c424d34, 5, 1, 0, 0, 32, 16, 8]       # a 32 x 16 x 8 grid: same cell count
         vp = ctypes.c_void_p(buf.ctypes.data)
         assert L.lbm_set_state(h, vp, nb.value) == lbm.EINVAL
         assert b"32x16x8" in L.lbm_last_error(h)
-        hdr[:8] = [0x4c424d33, 5, 1, 1, 0, 16, 32, 8]       # FP16 state into an FP32 context
+        hdr[:8] = [0x4c424d34, 5, 1, 1, 0, 16, 32, 8]       # FP16 state into an FP32 context
         assert L.lbm_set_state(h, vp, nb.value) == lbm.EINVAL
         assert b"storage" in L.lbm_last_error(h)
         hdr[:8] = [0x4c424d32, 5, 1, 0, 0, 16, 32, 8]       # an earlier (plane-layout) state: refused
         assert L.lbm_set_state(h, vp, nb.value) == lbm.EINVAL
+        hdr[:8] = [0x4c424d33, 5, 1, 0, 0, 16, 32, 8]       # 64-cell FP32 blocks (earlier layout): refused
+        assert L.lbm_set_state(h, vp, nb.value) == lbm.EINVAL
         assert L.lbm_set_state(h, vp, nb.value - 1) == lbm.EINVAL   # short buffer
         # a matching header passes the header checks and stops at the attach check
-        hdr[:8] = [0x4c424d33, 5, 1, 0, 0, 16, 32, 8]
+        hdr[:8] = [0x4c424d34, 5, 1, 0, 0, 16, 32, 8]
         assert L.lbm_set_state(h, vp, nb.value) == lbm.ESTATE
     finally:
         assert L.lbm_destroy(h) == lbm.OK
