@@ -58,9 +58,14 @@ __device__ __forceinline__ float relu(float x) { return __int_as_float(max(__flo
 // logarithm uses log(1 + e) = 2 atanh(s), s = e / (2 + e) in (0, 1/3], and
 // the odd series 2 (s + s^3/3 + ... + s^15/15): the first dropped term is
 // below s^16/17 < 2e-9 of the sum, and the result keeps its relative
-// accuracy for tiny e, where log(1 + e) would round to zero.
+// accuracy for tiny e, where log(1 + e) would round to zero. e comes from the
+// hardware base-2 exponential of -|z| log2(e) (two instructions instead of
+// the thirteen of the range-reduced expf): its relative error, about
+// |z| 2^-24 from the rounded product, stays below 1e-6 for |z| < 16; beyond
+// |z| = 87, e < 2^-126, whether kept or flushed, leaves max(z, 0) (or a
+// viscosity below 1e-37) to FP32 precision.
 __device__ __forceinline__ float softplusf(float z) {
-    const float e = expf(-fabsf(z));
+    const float e = __expf(-fabsf(z));
     const float s = e * frcp(2.0f + e), t = s * s;
     float p = 1.0f / 15.0f;
     p = fmaf(p, t, 1.0f / 13.0f);
