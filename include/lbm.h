@@ -368,8 +368,9 @@ int lbm_copy_probe(const void *d_src, void *d_dst, size_t bytes, void *stream);
  * neighbours' slots, periodic wrap) with the same tiling and addressing and
  * no collision. Moves 27 * 2 * sizeof(storage) bytes per cell. The
  * populations are left permuted: initialise again before stepping. Needs the
- * 32-bit offsets of the fast path (one z plane of the store, ny * ceil(nx/64)
- * blocks of 27 * 64 values, below 4 GiB); otherwise LBM_EINVAL. */
+ * 32-bit offsets of the fast path (one z plane of the store, ny * ceil(nx/W)
+ * blocks of 27 * W values, W as in lbm_required_bytes, below 4 GiB);
+ * otherwise LBM_EINVAL. */
 int lbm_pattern_probe(lbm_ctx *ctx, int parity);
 
 const char *lbm_strerror(int code);
