@@ -92,6 +92,24 @@ def _unattached_context(nx, ny, nz, storage=0):
     return L, h
 
 
+def test_population_store_size_follows_the_blocked_layout():
+    """lbm_required_bytes reports the blocked store the header documents:
+    nz * ny * ceil(nx / W) * 27 * W values of the storage type, W = 32 for
+    FP32 and 64 for FP16 / BF16, rounded up to 256 bytes (x rows padded to
+    whole blocks). Host-only: the context is never attached."""
+    from paper_2402_13171_amd import lbm
+    for storage, esize, w in ((0, 4, 32), (1, 2, 64), (2, 2, 64)):
+        for nx, ny, nz in ((64, 8, 4), (33, 5, 3), (80, 7, 2), (2, 2, 2)):
+            L, h = _unattached_context(nx, ny, nz, storage)
+            try:
+                pb, ab = ctypes.c_size_t(), ctypes.c_size_t()
+                assert L.lbm_required_bytes(h, ctypes.byref(pb), ctypes.byref(ab)) == lbm.OK
+                raw = nz * ny * (-(-nx // w)) * 27 * w * esize
+                assert pb.value == -(-raw // 256) * 256, (storage, nx, ny, nz, pb.value)
+            finally:
+                assert L.lbm_destroy(h) == lbm.OK
+
+
 def test_state_of_another_shape_or_storage_is_refused_before_device_work():
     """The checkpoint header (eight int64: magic, time, parity, storage,
     force-box bytes, nx, ny, nz) is checked before the context is even
